@@ -603,8 +603,10 @@ int orc_merge_scores(int n, const int *out_ptr, const int *out_idx, const int *l
 /* count is reached", with pointer-based tracking of Sec. III-A (d)).    */
 /* Candidates in ascending (floor(dS_local*2^20), c); merging joins the  */
 /* set of c into the set of its partner; pairs already joined or without */
-/* a partner are skipped.  New labels are the ranks of the surviving     */
-/* representatives in ascending id order.  Returns the new block count.  */
+/* a partner are skipped.  New labels number the merged groups in the   */
+/* ascending order of their smallest member block (a canonical order     */
+/* that does not depend on the order of the unions).  Returns the new   */
+/* block count.                                                          */
 /* ------------------------------------------------------------------ */
 static int uf_find(int *parent, int a)
 {
@@ -636,11 +638,18 @@ int orc_merge_apply(int C, const int *partner, const double *dS_local, int n_mer
         parent[a] = b;
         ++done;
     }
+    /* smallest member of each group, then groups numbered in that order */
+    int *low = (int *)malloc(sizeof(int) * (size_t)C);
+    for (int c = 0; c < C; ++c) low[c] = C;
+    for (int c = 0; c < C; ++c) {
+        int root = uf_find(parent, c);
+        if (c < low[root]) low[root] = c;
+    }
     int next = 0;
     int *rank = (int *)malloc(sizeof(int) * (size_t)C);
-    for (int c = 0; c < C; ++c) rank[c] = (uf_find(parent, c) == c) ? next++ : -1;
-    for (int c = 0; c < C; ++c) map[c] = rank[uf_find(parent, c)];
-    free(rank); free(parent); free(cand);
+    for (int c = 0; c < C; ++c) rank[c] = (low[uf_find(parent, c)] == c) ? next++ : -1;
+    for (int c = 0; c < C; ++c) map[c] = rank[low[uf_find(parent, c)]];
+    free(low); free(rank); free(parent); free(cand);
     return next;
 }
 

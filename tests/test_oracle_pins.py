@@ -410,19 +410,24 @@ def test_merge_apply_union_find_by_hand():
     # a pair already joined does not count; unpartnered blocks are skipped
     newC, m = O.merge_apply(np.array([1, 0, -1, 2]), np.array([0.1, 0.2, np.inf, 0.3]), 2)
     assert newC == 2 and list(m) == [0, 0, 1, 1]
-    # ties on the score are broken by block id
-    # (block 0 joins 2; surviving roots 1, 2 become labels 0, 1)
+    # ties on the score are broken by block id; groups are numbered by their smallest block
+    # (block 0 joins 2: groups {0, 2} and {1})
     newC, m = O.merge_apply(np.array([2, 2, 0]), np.array([1.0, 1.0, 1.0]), 1)
-    assert newC == 2 and list(m) == [1, 0, 1]
+    assert newC == 2 and list(m) == [0, 1, 0]
     # differences below 2^-20 nats are ties as well
     newC, m = O.merge_apply(np.array([2, 2, 0]), np.array([1.0 + 2**-23, 1.0, 5.0]), 1)
-    assert newC == 2 and list(m) == [1, 0, 1]
-    # a difference above 2^-20 nats orders the candidates
+    assert newC == 2 and list(m) == [0, 1, 0]
+    # a difference above 2^-20 nats orders the candidates: block 1 joins 2 first
     newC, m = O.merge_apply(np.array([2, 2, 0]), np.array([1.0 + 2**-19, 1.0, 5.0]), 1)
     assert newC == 2 and list(m) == [0, 1, 1]
     # running out of candidates leaves more blocks than asked
     newC, m = O.merge_apply(np.array([-1, -1, 0]), np.array([np.inf, np.inf, 0.0]), 2)
     assert newC == 2 and list(m) == [0, 1, 0]
+    # a 3-cycle of proposals: the last edge of the cycle closes it and is skipped
+    newC, m = O.merge_apply(np.array([1, 2, 0, 2]), np.array([0.3, 0.1, 0.2, 0.4]), 3)
+    assert newC == 1 and list(m) == [0, 0, 0, 0]
+    newC, m = O.merge_apply(np.array([1, 2, 0, 2]), np.array([0.3, 0.1, 0.2, 0.9]), 2)
+    assert newC == 2 and list(m) == [0, 0, 0, 1]
 
 
 def test_compaction_by_hand():
