@@ -1,0 +1,165 @@
+// sbp_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sbp_device.h"
+
+namespace sbp {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+#define SBP_HIP_CHECK(call)                                                                     \
+    do {                                                                                        \
+        hipError_t err_ = (call);                                                               \
+        if (err_ != hipSuccess)                                                                 \
+            return ::sbp::fail(-5, std::string(#call) + ": " + hipGetErrorString(err_));        \
+    } while (0)
+#define SBP_LAUNCH_CHECK()                                                                      \
+    do {                                                                                        \
+        hipError_t err_ = hipGetLastError();                                                    \
+        if (err_ != hipSuccess)                                                                 \
+            return ::sbp::fail(-5, std::string("kernel launch: ") + hipGetErrorString(err_));   \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timing (sbp_engine.hip)
+// Records an event pair around a launch when profiling is on.
+struct ProfileScope {
+    int slot = -1;
+    hipStream_t s;
+    const char *name_ = nullptr;
+    ProfileScope(const char *name, hipStream_t stream);
+    ~ProfileScope();
+};
+
+// ---------------------------------------------------------------- bump allocator over caller memory
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool dry = false;  // size query only
+    Arena() = default;
+    Arena(void *b, size_t c) : base((char *)b), cap(c) {}
+    static Arena measure() {
+        Arena a;
+        a.dry = true;
+        a.cap = SIZE_MAX;
+        return a;
+    }
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        T *p = dry ? nullptr : (T *)(base + used);
+        used += bytes;
+        return p;
+    }
+    bool ok() const { return used <= cap; }
+};
+
+inline int ceil_log2(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < x) ++b;
+    return b;
+}
+inline int grid_for(long long n, int block, int max_blocks = 65535 * 16) {
+    long long g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > max_blocks) g = max_blocks;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------- primitives (sbp_prims.hip)
+// Workspace of an exclusive scan of n elements.
+size_t scan_temp_bytes(long long n);
+// out[i] = sum_{j<i} in[j] (int64 out); *total (device, nullable) = sum of all.
+int scan_exclusive_i32(const int *in, long long *out, long long n, long long *total, void *temp, hipStream_t s);
+int scan_exclusive_i64(const long long *in, long long *out, long long n, long long *total, void *temp,
+                       hipStream_t s);
+// Stable LSD radix sort of n keys (< 2^bits) with optional 64-bit values.
+// Results end in keys/vals (ping-pong through the alt buffers).
+size_t radix_temp_bytes(long long n);
+int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *vals_alt, long long n, int bits,
+               void *temp, hipStream_t s);
+int fill_i32(int *p, int value, long long n, hipStream_t s);
+int fill_i64(long long *p, long long value, long long n, hipStream_t s);
+int iota_i32(int *p, long long n, hipStream_t s);
+
+// ---------------------------------------------------------------- union (batched) sparse blockmodel
+struct SparseBM {
+    int Ctot;       // blocks in the union
+    long long cap;  // entry capacity (>= union edge count)
+    int *rptr;      // [Ctot+1] rows of M (entries sorted by column)
+    int *rcol, *rval;
+    int *cptr;      // [Ctot+1] columns of M (entries sorted by row)
+    int *crow, *cval;
+    int *scol, *scum;  // [2 cap] rows of M + M^T in ascending column, running sums
+    int *dout, *din;   // [Ctot]
+    long long *nnz;    // device scalar
+};
+
+// Scratch of one union build / step (capacities: cap >= max(total edges,
+// total vertices); per-graph arrays hold G entries).
+struct UnionScratch {
+    uint64_t *k0, *k1, *v0, *v1;  // sort buffers [cap]
+    long long *s0, *s1;           // scan outputs [cap + 1]
+    int *i0, *i1;                 // int scratch [cap]
+    void *temp;                   // primitive temp
+    double *dl_part;              // per-chunk partial sums
+    double *dl;                   // per-graph DL [G]
+    int *nb;                      // accepted new label per union vertex, else -1
+    int *hub_scratch;             // hub_slots x hub_scratch_ints_per_slot()
+    int hub_slots;
+    int *mpos, *mj0, *mj1, *mm0, *mm1, *mcyc, *mlow, *mmap;  // merge application [cap]
+    int *gC;                      // per-graph new block count [G]
+};
+
+int build_union_sparse(const GDev *dG, const StepMeta &m, SparseBM &bm, UnionScratch &ws, hipStream_t s);
+int union_dl(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch &ws, hipStream_t s);
+struct SweepTraceDev {
+    int *prop;
+    double *dS, *lnH, *margin;
+    signed char *accept;
+    signed char *status;  // -1 own block proposed, 0 rejected, 1 accepted
+};
+int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch &ws, const SweepTraceDev &tr,
+                hipStream_t s);
+int union_merge_scores(const GDev *dG, const StepMeta &m, const SparseBM &bm, int *partner, double *dS, double *dSl,
+                       hipStream_t s);
+// Merge application of the merging graphs: new labels per merge item in
+// ws.mmap, new block counts in ws.gC.
+int union_merge_apply(const GDev *dG, const StepMeta &m, const int *partner, const double *dSl, UnionScratch &ws,
+                      hipStream_t s);
+// Compaction of the compacting graphs: map in ws.mmap, counts in ws.gC.
+int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream_t s);
+// lab[v] <- map[blkstart[g] + lab[v]] for the vertex items of vstart.
+int union_relabel(const GDev *dG, int G, const int *vstart, int n_vitems, const int *blkstart, const int *map,
+                  hipStream_t s);
+size_t hub_scratch_ints_per_slot();
+int dl_chunks_of(int e, int C);
+
+// ---------------------------------------------------------------- dense tier (sbp_dense.hip)
+struct DenseBM {
+    int C;
+    int *M;           // [C*C]
+    int *cdf;         // [C*C] running sums of e_ts = M_ts + M_st over s
+    int *dout, *din;  // [C]
+    double *dl;       // [1]
+};
+struct DenseScratch {
+    int *delta;             // [C*C] change of M of one batch (kept zero between batches)
+    int nwg;                // workgroups of the evaluation grid
+    int *nb;                // [n] accepted new label, else -1
+    long long *stats_part;  // [nwg][4]
+    double *sum_part;       // [nwg]
+};
+int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s);
+int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr,
+                      sbp_sweep_stats_dev *stats, hipStream_t s);
+int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *dS, double *dSl, hipStream_t s);
+int dense_workgroups();
+
+}  // namespace sbp

@@ -1,0 +1,995 @@
+// sbp_sparse.hip -- sparse blockmodel tier over a batch of graphs (gfx950).
+//
+// The graphs of a step are laid side by side: graph g's blocks occupy union
+// ids [boff, boff + C) and its edges union slots [eoff, eoff + e).  The union
+// blockmodel is block diagonal, so one build serves every graph, and every
+// per-graph result depends only on that graph's data (rows, chunk borders and
+// reduction trees are taken relative to the graph's own indices).
+//
+//   M (Sec. II-A) ......... rows: rptr/rcol/rval, columns: cptr/crow/cval
+//                           (the hashmap rows and transpose of Sec. III-A (a,b)
+//                           as sorted arrays)
+//   proposal tables ....... row t of M + M^T in ascending column with running
+//                           sums (scol/scum), so a draw from e_t. is a search
+//   DL (Eq. 1, Eq. 2) ..... chunked FP64 reduction per graph
+//   sweep (Alg. 2) ........ wave per vertex with <= 256 edge ends, workgroup
+//                           per hub; neighbour blocks aggregated by a bitonic
+//                           sort (the sparse change vector of Sec. III-A (c))
+//   merges (Alg. 1) ....... wave per block for scoring; application as a
+//                           parallel greedy union over the candidate
+//                           pseudoforest (pointer jumping)
+#include "sbp_internal.h"
+
+namespace sbp {
+
+namespace {
+
+constexpr int BLK = 256;
+
+// ---------------------------------------------------------------- lookups
+__device__ __forceinline__ int row_get(const int *__restrict__ ptr, const int *__restrict__ idx,
+                                       const int *__restrict__ val, int a, int b) {
+    int lo = ptr[a], hi = ptr[a + 1];
+    const int end = hi;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (idx[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && idx[lo] == b) ? val[lo] : 0;
+}
+__device__ __forceinline__ int m_get(const SparseBM &bm, int a, int b) { return row_get(bm.rptr, bm.rcol, bm.rval, a, b); }
+__device__ __forceinline__ int mt_get(const SparseBM &bm, int b, int a) { return row_get(bm.cptr, bm.crow, bm.cval, b, a); }
+
+// smallest s whose running sum of e_ts (ascending s) exceeds x, 0 <= x < d_t
+__device__ __forceinline__ int s_draw(const SparseBM &bm, int t, long long x) {
+    int lo = bm.rptr[t] + bm.cptr[t], hi = bm.rptr[t + 1] + bm.cptr[t + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)bm.scum[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return bm.scol[lo];
+}
+
+__device__ __forceinline__ double model_terms(double E, double N, double C) {
+    const double c2 = C * C;
+    return xlogx(E + c2) - xlogx(E) - xlogx(c2) + N * log(C);
+}
+
+// ---------------------------------------------------------------- build
+__global__ void k_edge_keys(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG, int Ntot, int Ctot,
+                            uint64_t *__restrict__ keys) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Ntot; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(vstart, nG, i);
+        const GDev &d = G[g];
+        const int v = i - d.voff;
+        const uint64_t base = (uint64_t)(d.boff + d.lab[v]) * (uint64_t)Ctot + (uint64_t)d.boff;
+        const int j0 = d.out_ptr[v], j1 = d.out_ptr[v + 1];
+        uint64_t *out = keys + d.eoff;
+        for (int j = j0; j < j1; ++j) out[j] = base + (uint64_t)d.lab[d.out_idx[j]];
+    }
+}
+
+__global__ void k_rle_flags(const uint64_t *__restrict__ keys, long long n, int *__restrict__ flags) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_rle_emit(const uint64_t *__restrict__ keys, const int *__restrict__ flags,
+                           const long long *__restrict__ pos, long long n, int Ctot, int *__restrict__ urow,
+                           int *__restrict__ rcol, int *__restrict__ start) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        if (!flags[i]) continue;
+        const long long k = pos[i];
+        const uint64_t key = keys[i];
+        urow[k] = (int)(key / (uint64_t)Ctot);
+        rcol[k] = (int)(key % (uint64_t)Ctot);
+        start[k] = (int)i;
+    }
+}
+
+__global__ void k_rle_count(const int *__restrict__ start, const long long *__restrict__ nnz_p, long long n,
+                            int *__restrict__ rval) {
+    const long long nnz = *nnz_p;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (long long)gridDim.x * blockDim.x)
+        rval[k] = (int)((k + 1 < nnz ? (long long)start[k + 1] : n) - start[k]);
+}
+
+// ptr[a] = first entry whose key is >= a, for a in [0, C]
+__global__ void k_lower_bounds(const int *__restrict__ keys, const long long *__restrict__ nnz_p, int C,
+                               int *__restrict__ ptr) {
+    const int nnz = (int)*nnz_p;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a <= C; a += gridDim.x * blockDim.x) {
+        int lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (keys[mid] < a) lo = mid + 1; else hi = mid;
+        }
+        ptr[a] = lo;
+    }
+}
+
+__global__ void k_csc_keys(const int *__restrict__ urow, const int *__restrict__ rcol, const int *__restrict__ rval,
+                           const long long *__restrict__ nnz_p, long long cap, int Ctot, uint64_t *__restrict__ k2,
+                           uint64_t *__restrict__ v2) {
+    const long long nnz = *nnz_p;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cap; k += (long long)gridDim.x * blockDim.x) {
+        if (k < nnz) {
+            k2[k] = (uint64_t)rcol[k];
+            v2[k] = ((uint64_t)(uint32_t)urow[k] << 32) | (uint32_t)rval[k];
+        } else {
+            k2[k] = (uint64_t)Ctot;
+            v2[k] = 0;
+        }
+    }
+}
+
+__global__ void k_csc_emit(const uint64_t *__restrict__ k2, const uint64_t *__restrict__ v2,
+                           const long long *__restrict__ nnz_p, int *__restrict__ ccol, int *__restrict__ crow,
+                           int *__restrict__ cval) {
+    const long long nnz = *nnz_p;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (long long)gridDim.x * blockDim.x) {
+        ccol[k] = (int)k2[k];
+        crow[k] = (int)(v2[k] >> 32);
+        cval[k] = (int)(v2[k] & 0xffffffffu);
+    }
+}
+
+// Wave per block t: degrees, then row t of M + M^T merged in ascending column
+// (row entries first on equal columns) with running sums.
+__global__ void __launch_bounds__(BLK) k_block_rows(SparseBM bm) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int t = wave; t < bm.Ctot; t += nwaves) {
+        const int r0 = bm.rptr[t], lr = bm.rptr[t + 1] - r0;
+        const int c0 = bm.cptr[t], lc = bm.cptr[t + 1] - c0;
+        int so = 0, si = 0;
+        for (int j = lane; j < lr; j += 64) so += bm.rval[r0 + j];
+        for (int j = lane; j < lc; j += 64) si += bm.cval[c0 + j];
+        so = wave_sum_i32(so);
+        si = wave_sum_i32(si);
+        if (lane == 0) {
+            bm.dout[t] = so;
+            bm.din[t] = si;
+        }
+        const int *A = bm.rcol + r0, *Av = bm.rval + r0;
+        const int *B = bm.crow + c0, *Bv = bm.cval + c0;
+        const int s0 = r0 + c0, L = lr + lc;
+        int carry = 0;
+        for (int base = 0; base < L; base += 64) {
+            const int q = base + lane;
+            int col = 0, val = 0;
+            if (q < L) {
+                int lo = q - lc > 0 ? q - lc : 0, hi = q < lr ? q : lr;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (A[mid] <= B[q - 1 - mid]) lo = mid + 1; else hi = mid;
+                }
+                const int i = lo, j = q - lo;
+                if (i < lr && (j >= lc || A[i] <= B[j])) {
+                    col = A[i];
+                    val = Av[i];
+                } else {
+                    col = B[j];
+                    val = Bv[j];
+                }
+            }
+            int x = val;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, SBP_WAVE);
+                if (lane >= o) x += y;
+            }
+            if (q < L) {
+                bm.scol[s0 + q] = col;
+                bm.scum[s0 + q] = carry + x;
+            }
+            carry += __shfl(x, 63, SBP_WAVE);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- description length
+constexpr int DL_CHUNK = 2048;
+
+__global__ void __launch_bounds__(BLK) k_dl_partial(const GDev *__restrict__ G, const int *__restrict__ chstart, int nG,
+                                                   int nchunks, SparseBM bm, double *__restrict__ part) {
+    __shared__ double ws[BLK / SBP_WAVE];
+    const int ch = blockIdx.x;
+    if (ch >= nchunks) return;
+    const int g = find_graph(chstart, nG, ch);
+    const GDev &d = G[g];
+    const int local = ch - chstart[g];
+    const int nE = (d.e + DL_CHUNK - 1) / DL_CHUNK;
+    double acc = 0.0;
+    if (local < nE) {
+        const int k0 = bm.rptr[d.boff], k1 = bm.rptr[d.boff + d.C];
+        for (int i = threadIdx.x; i < DL_CHUNK; i += BLK) {
+            const int k = k0 + local * DL_CHUNK + i;
+            if (k < k1) acc += xlogx((double)bm.rval[k]);
+        }
+    } else {
+        const int base = (local - nE) * DL_CHUNK;
+        for (int i = threadIdx.x; i < DL_CHUNK; i += BLK) {
+            const int x = base + i;
+            if (x < d.C) acc -= xlogx((double)bm.dout[d.boff + x]);
+            else if (x < 2 * d.C) acc -= xlogx((double)bm.din[d.boff + x - d.C]);
+        }
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < BLK / SBP_WAVE; ++w) t += ws[w];
+        part[ch] = t;
+    }
+}
+
+__global__ void k_dl_final(const GDev *__restrict__ G, const int *__restrict__ chstart, int nG, int nchunks,
+                           const double *__restrict__ part, double *__restrict__ dl) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nG) return;
+    const GDev &d = G[g];
+    const int c0 = chstart[g], c1 = g + 1 < nG ? chstart[g + 1] : nchunks;
+    double L = 0.0;
+    for (int c = c0; c < c1; ++c) L += part[c];
+    dl[g] = model_terms((double)d.e, (double)d.n, (double)d.C) - L;
+}
+
+// ---------------------------------------------------------------- vertex moves
+struct MoveOut {
+    int s;  // proposed block (union id)
+    double dS, lnH, margin;
+    bool accept;
+};
+
+// Proposal of the move of v (union block r), identical on every lane.
+__device__ __forceinline__ int propose(const GDev &d, const SparseBM &bm, int v, int r, int kout, int kin,
+                                       const Words4 &W) {
+    const int k = kout + kin;
+    const long long eC = (long long)d.eps * d.C;
+    if (k == 0) return d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+    const int j = (int)draw_idx(W.w[0], (uint64_t)k);
+    const int u = j < kout ? d.out_idx[d.out_ptr[v] + j] : d.in_idx[d.in_ptr[v] + (j - kout)];
+    const int t = d.boff + d.lab[u];
+    const long long dt = (long long)bm.dout[t] + bm.din[t];
+    if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) return d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+    return s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt));
+}
+
+// DL change and Hastings term of moving v from r to s (union ids), given the
+// distinct neighbour blocks (ascending) with out/in edge counts; evaluated by
+// one wave, identical on every lane afterwards.
+__device__ MoveOut move_terms(const GDev &d, const SparseBM &bm, int r, int s, const int *dt, const int *dko,
+                              const int *dki, int D, int ell, int kout, int kin, double lnu) {
+    const int lane = threadIdx.x & 63;
+    const double eps = (double)d.eps;
+    const double epsC = (double)d.eps * (double)d.C;
+    double dL = 0.0, qf = 0.0, qr = 0.0;
+    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
+    for (int i = lane; i < D; i += 64) {
+        const int t = dt[i], ko = dko[i], ki = dki[i];
+        if (t == r) {
+            ko_r = ko;
+            ki_r = ki;
+            continue;
+        }
+        if (t == s) {
+            ko_s = ko;
+            ki_s = ki;
+            continue;
+        }
+        const int Mrt = m_get(bm, r, t), Mst = m_get(bm, s, t);
+        const int Mtr = m_get(bm, t, r), Mts = m_get(bm, t, s);
+        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
+        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
+        const double kt = (double)(ko + ki);
+        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
+        qf += kt * (((double)(Mts + Mst) + eps) / den);
+        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+    }
+    ko_r = wave_sum_i32(ko_r);
+    ki_r = wave_sum_i32(ki_r);
+    ko_s = wave_sum_i32(ko_s);
+    ki_s = wave_sum_i32(ki_s);
+    if (lane == 0) {
+        const int Mrr = m_get(bm, r, r), Mrs = m_get(bm, r, s), Msr = m_get(bm, s, r), Mss = m_get(bm, s, s);
+        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
+        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
+        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
+        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
+        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
+        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
+        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
+        const double k = (double)(kout + kin);
+        const double d_r = dor + dir, d_s = dos + dis;
+        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
+        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
+        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
+        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
+        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
+        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
+    }
+    dL = wave_sum(dL);
+    qf = wave_sum(qf);
+    qr = wave_sum(qr);
+    MoveOut o;
+    o.s = s;
+    o.dS = -dL;
+    o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
+    const double z = -d.beta * o.dS + o.lnH;
+    o.margin = z - lnu;
+    o.accept = lnu < z;
+    return o;
+}
+
+__device__ __forceinline__ void record_move(const GDev &d, int v, int r, const MoveOut &o, bool noop, int *nb,
+                                            const SweepTraceDev &tr) {
+    const int u = d.voff + v;
+    const bool acc = !noop && o.accept;
+    nb[u] = acc ? o.s - d.boff : -1;
+    if (tr.prop) tr.prop[u] = o.s - d.boff;
+    if (tr.dS) tr.dS[u] = noop ? 0.0 : o.dS;
+    if (tr.lnH) tr.lnH[u] = noop ? 0.0 : o.lnH;
+    if (tr.margin) tr.margin[u] = noop ? 0.0 : o.margin;
+    if (tr.accept) tr.accept[u] = acc ? 1 : 0;
+    if (tr.status) tr.status[u] = noop ? -1 : (acc ? 1 : 0);
+}
+
+constexpr int LEAF_WAVES = 4;
+constexpr int KEY_PAD = 0x7fffffff;
+
+// Wave per vertex with at most 256 edge ends.
+__global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__restrict__ G, const int *__restrict__ starts,
+                                                               int nG, int n_items, SparseBM bm, int *__restrict__ nb,
+                                                               SweepTraceDev tr) {
+    __shared__ int K[LEAF_WAVES][SBP_LEAF_MAX];
+    __shared__ int Dt[LEAF_WAVES][SBP_LEAF_MAX], Dko[LEAF_WAVES][SBP_LEAF_MAX], Dki[LEAF_WAVES][SBP_LEAF_MAX];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * LEAF_WAVES + wv, nw = gridDim.x * LEAF_WAVES;
+    int *Kw = K[wv];
+    const uint64_t below = lanemask_lt();
+    for (int item = gw; item < n_items; item += nw) {
+        const int g = find_graph(starts, nG, item);
+        const GDev &d = G[g];
+        const int v = item - starts[g];
+        if ((v % d.n_batches) != d.batch) continue;
+        if (d.out_ptr[v + 1] - d.out_ptr[v] + d.in_ptr[v + 1] - d.in_ptr[v] > SBP_LEAF_MAX) continue;
+        const int r = d.boff + d.lab[v];
+        const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
+        const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
+        const int k = kout + kin;
+        const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
+        const double lnu = log(draw_unit(W.w[3]));
+        const int s = propose(d, bm, v, r, kout, kin, W);
+        if (s == r) {
+            MoveOut o;
+            o.s = s;
+            if (lane == 0) record_move(d, v, r, o, true, nb, tr);
+            continue;
+        }
+        // edge-end keys 2 t + dir; self-loop ends and padding sort last
+        int ell = 0;
+        int m = 2;
+        while (m < k) m <<= 1;
+        for (int j = lane; j < m; j += 64) {
+            int key = KEY_PAD;
+            if (j < k) {
+                const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
+                if (u == v) {
+                    if (j < kout) ++ell;
+                } else {
+                    key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
+                }
+            }
+            Kw[j] = key;
+        }
+        ell = wave_sum_i32(ell);
+        wave_sync_lds();
+        for (int size = 2; size <= m; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int q = lane; q < (m >> 1); q += 64) {
+                    const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
+                    const bool asc = (i & size) == 0;
+                    const int a = Kw[i], b = Kw[j];
+                    if ((a > b) == asc) {
+                        Kw[i] = b;
+                        Kw[j] = a;
+                    }
+                }
+                wave_sync_lds();
+            }
+        }
+        // run-length encode into (t, ko, ki) with 4 x 64-bit masks
+        const int kk = k - 2 * ell;
+        uint64_t sm[4], em[4];
+        int key_c[4];
+        bool st_c[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int p = 64 * c + lane;
+            const int key = p < kk ? Kw[p] : KEY_PAD;
+            const int prev = (p > 0 && p < kk) ? Kw[p - 1] : -2;
+            const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
+            sm[c] = __ballot(st);
+            em[c] = __ballot(p < kk && !(key & 1));
+            key_c[c] = key;
+            st_c[c] = st;
+        }
+        int D = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) D += __popcll(sm[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!st_c[c]) continue;
+            const int p = 64 * c + lane;
+            int idx = 0;
+            for (int c2 = 0; c2 < c; ++c2) idx += __popcll(sm[c2]);
+            idx += __popcll(sm[c] & below);
+            int end = kk;
+            const uint64_t after = (lane == 63) ? 0ull : (sm[c] & ~((2ull << lane) - 1));
+            if (after) {
+                end = 64 * c + __builtin_ctzll(after);
+            } else {
+                for (int c2 = c + 1; c2 < 4; ++c2)
+                    if (sm[c2]) {
+                        end = 64 * c2 + __builtin_ctzll(sm[c2]);
+                        break;
+                    }
+            }
+            auto evens_below = [&](int x) {
+                int e = 0;
+                for (int c2 = 0; c2 < 4; ++c2) {
+                    if (64 * (c2 + 1) <= x) e += __popcll(em[c2]);
+                    else {
+                        if (x > 64 * c2) e += __popcll(em[c2] & (~0ull >> (64 - (x - 64 * c2))));
+                        break;
+                    }
+                }
+                return e;
+            };
+            const int ko = evens_below(end) - evens_below(p);
+            Dt[wv][idx] = key_c[c] >> 1;
+            Dko[wv][idx] = ko;
+            Dki[wv][idx] = (end - p) - ko;
+        }
+        wave_sync_lds();
+        const MoveOut o = move_terms(d, bm, r, s, Dt[wv], Dko[wv], Dki[wv], D, ell, kout, kin, lnu);
+        if (lane == 0) record_move(d, v, r, o, false, nb, tr);
+        wave_sync_lds();
+    }
+}
+
+// Workgroup per hub (more than 256 edge ends): keys sorted in global scratch.
+constexpr int HUB_THREADS = 1024;
+constexpr size_t HUB_SLOT_INTS = 4 * (size_t)SBP_MAX_DEGREE_DEV;
+__global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restrict__ G, const int *__restrict__ starts,
+                                                           int nG, int n_items, SparseBM bm, int *__restrict__ nb,
+                                                           SweepTraceDev tr, int *__restrict__ scratch) {
+    __shared__ int red[HUB_THREADS / 64];
+    __shared__ int s_ell, s_D;
+    int *Kg = scratch + (size_t)blockIdx.x * HUB_SLOT_INTS;
+    int *Dt = Kg + SBP_MAX_DEGREE_DEV;
+    int *Dko = Dt + SBP_MAX_DEGREE_DEV;
+    int *Dki = Dko + SBP_MAX_DEGREE_DEV;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int g = find_graph(starts, nG, item);
+        const GDev &d = G[g];
+        const int v = d.hub[item - starts[g]];
+        if ((v % d.n_batches) != d.batch) continue;
+        const int r = d.boff + d.lab[v];
+        const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
+        const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
+        const int k = kout + kin;
+        if (k > SBP_MAX_DEGREE_DEV) {  // beyond the scratch (validation rejects such graphs): no move
+            if (tid == 0) nb[d.voff + v] = -1;
+            continue;
+        }
+        const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
+        const double lnu = log(draw_unit(W.w[3]));
+        const int s = propose(d, bm, v, r, kout, kin, W);
+        if (s == r) {
+            if (tid == 0) {
+                MoveOut o;
+                o.s = s;
+                record_move(d, v, r, o, true, nb, tr);
+            }
+            __syncthreads();
+            continue;
+        }
+        int m = 2;
+        while (m < k) m <<= 1;
+        int ell = 0;
+        for (int j = tid; j < m; j += HUB_THREADS) {
+            int key = KEY_PAD;
+            if (j < k) {
+                const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
+                if (u == v) {
+                    if (j < kout) ++ell;
+                } else {
+                    key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
+                }
+            }
+            Kg[j] = key;
+        }
+        ell = wave_sum_i32(ell);
+        if (lane == 0) red[wv] = ell;
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int w = 0; w < HUB_THREADS / 64; ++w) t += red[w];
+            s_ell = t;
+        }
+        for (int size = 2; size <= m; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int q = tid; q < (m >> 1); q += HUB_THREADS) {
+                    const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
+                    const bool asc = (i & size) == 0;
+                    const int a = Kg[i], b = Kg[j];
+                    if ((a > b) == asc) {
+                        Kg[i] = b;
+                        Kg[j] = a;
+                    }
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
+        }
+        ell = s_ell;
+        const int kk = k - 2 * ell;
+        // run starts, in order, by wave 0 scanning 64 positions at a time
+        if (wv == 0) {
+            int D = 0;
+            int pend_idx = -1, pend_p = 0, pend_key = 0, evens = 0, pend_evens = 0;
+            for (int base = 0; base < kk; base += 64) {
+                const int p = base + lane;
+                const int key = p < kk ? Kg[p] : KEY_PAD;
+                const int prev = (p > 0 && p < kk) ? Kg[p - 1] : -2;
+                const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
+                const bool ev = p < kk && !(key & 1);
+                const uint64_t sm = __ballot(st), em = __ballot(ev);
+                // close runs: every start in this chunk ends the previous run
+                uint64_t rest = sm;
+                while (rest) {
+                    const int b = __builtin_ctzll(rest);
+                    rest &= rest - 1;
+                    const int pos = base + b;
+                    const int ev_before = evens + __popcll(em & ((b ? (~0ull >> (64 - b)) : 0ull)));
+                    if (pend_idx >= 0 && lane == 0) {
+                        const int ko = ev_before - pend_evens;
+                        Dt[pend_idx] = pend_key >> 1;
+                        Dko[pend_idx] = ko;
+                        Dki[pend_idx] = (pos - pend_p) - ko;
+                    }
+                    pend_idx = D++;
+                    pend_p = pos;
+                    pend_key = __shfl(key, b, SBP_WAVE);
+                    pend_evens = ev_before;
+                }
+                evens += __popcll(em);
+            }
+            if (pend_idx >= 0 && lane == 0) {
+                const int ko = evens - pend_evens;
+                Dt[pend_idx] = pend_key >> 1;
+                Dko[pend_idx] = ko;
+                Dki[pend_idx] = (kk - pend_p) - ko;
+            }
+            if (lane == 0) s_D = D;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (wv == 0) {
+            const MoveOut o = move_terms(d, bm, r, s, Dt, Dko, Dki, s_D, ell, kout, kin, lnu);
+            if (lane == 0) record_move(d, v, r, o, false, nb, tr);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_sweep_apply(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG, int Ntot,
+                              const int *__restrict__ nb) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Ntot; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(vstart, nG, i);
+        const GDev &d = G[g];
+        if (d.action != ACT_SWEEP) continue;
+        const int v = i - d.voff;
+        if ((v % d.n_batches) != d.batch) continue;
+        const int x = nb[i];
+        if (x >= 0) d.lab[v] = x;
+    }
+}
+
+// ---------------------------------------------------------------- merge scoring
+// -(change of L) when union blocks A and B become one block (Alg. 1).
+__device__ double merge_dL(const SparseBM &bm, int A, int B) {
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    {
+        const int la = bm.rptr[A + 1] - bm.rptr[A], lb = bm.rptr[B + 1] - bm.rptr[B];
+        const int X = la <= lb ? A : B, Y = la <= lb ? B : A;
+        const int x0 = bm.rptr[X], x1 = bm.rptr[X + 1];
+        for (int q = x0 + lane; q < x1; q += 64) {
+            const int t = bm.rcol[q];
+            if (t == A || t == B) continue;
+            const int y = m_get(bm, Y, t);
+            if (y) {
+                const int x = bm.rval[q];
+                acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+            }
+        }
+    }
+    {
+        const int la = bm.cptr[A + 1] - bm.cptr[A], lb = bm.cptr[B + 1] - bm.cptr[B];
+        const int X = la <= lb ? A : B, Y = la <= lb ? B : A;
+        const int x0 = bm.cptr[X], x1 = bm.cptr[X + 1];
+        for (int q = x0 + lane; q < x1; q += 64) {
+            const int t = bm.crow[q];
+            if (t == A || t == B) continue;
+            const int y = mt_get(bm, Y, t);
+            if (y) {
+                const int x = bm.cval[q];
+                acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+            }
+        }
+    }
+    if (lane == 0) {
+        const int a = m_get(bm, A, A), b = m_get(bm, A, B), e = m_get(bm, B, A), g = m_get(bm, B, B);
+        acc += xlogx((double)(a + b + e + g)) - xlogx((double)a) - xlogx((double)b) - xlogx((double)e) -
+               xlogx((double)g);
+        const double oa = bm.dout[A], ob = bm.dout[B], ia = bm.din[A], ib = bm.din[B];
+        acc -= xlogx(oa + ob) - xlogx(oa) - xlogx(ob);
+        acc -= xlogx(ia + ib) - xlogx(ia) - xlogx(ib);
+    }
+    return wave_sum(acc);
+}
+
+__global__ void __launch_bounds__(BLK) k_merge_scores(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG,
+                                                     int n_items, SparseBM bm, int *__restrict__ partner,
+                                                     double *__restrict__ dS, double *__restrict__ dSl) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int item = gw; item < n_items; item += nw) {
+        const int g = find_graph(bstart, nG, item);
+        const GDev &d = G[g];
+        const int c = item - bstart[g];
+        const int A = d.boff + c;
+        const int C = d.C;
+        const long long dc = (long long)bm.dout[A] + bm.din[A];
+        const long long eC = (long long)d.eps * C;
+        int best = -1;
+        double bestL = 0.0;
+        long long bestkey = INT64_MAX;
+        for (int j = 0; j < d.proposals && C > 1; ++j) {
+            const Words4 W = draw_words(d.seed, (uint32_t)c, d.phase, (uint32_t)(2 * j), 1u);
+            int cp;
+            if (dc == 0) {
+                const int kk = (int)draw_idx(W.w[2], (uint64_t)(C - 1));
+                cp = kk + (kk >= c);
+            } else {
+                const int t = s_draw(bm, A, draw_idx(W.w[0], (uint64_t)dc));
+                const long long dt = (long long)bm.dout[t] + bm.din[t];
+                if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) {
+                    const int kk = (int)draw_idx(W.w[2], (uint64_t)(C - 1));
+                    cp = kk + (kk >= c);
+                } else {
+                    cp = s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt)) - d.boff;
+                }
+            }
+            if (cp == c) continue;
+            const double local = -merge_dL(bm, A, d.boff + cp);
+            const long long key = merge_rank(local);
+            if (key < bestkey) {
+                bestkey = key;
+                best = cp;
+                bestL = local;
+            }
+        }
+        if (lane == 0) {
+            const double inf = __builtin_huge_val();
+            partner[d.boff + c] = best;
+            dSl[d.boff + c] = best < 0 ? inf : bestL;
+            const double off = C > 1 ? model_terms((double)d.e, (double)d.n, (double)(C - 1)) -
+                                           model_terms((double)d.e, (double)d.n, (double)C)
+                                     : 0.0;
+            dS[d.boff + c] = best < 0 ? inf : bestL + off;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- merge application
+// Items are the blocks of the merging graphs, item i = bstart[g] + c.
+__global__ void k_mkeys(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG, int n_items,
+                        const double *__restrict__ dSl, uint64_t *__restrict__ key, uint64_t *__restrict__ val) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(bstart, nG, i);
+        const GDev &d = G[g];
+        const long long r = merge_rank(dSl[d.boff + (i - bstart[g])]);
+        key[i] = (uint64_t)r ^ 0x8000000000000000ull;
+        val[i] = (uint64_t)i;
+    }
+}
+__global__ void k_mgraph_keys(const int *__restrict__ bstart, int nG, int n_items, const uint64_t *__restrict__ val,
+                              uint64_t *__restrict__ key) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_items; q += gridDim.x * blockDim.x)
+        key[q] = (uint64_t)find_graph(bstart, nG, (int)val[q]);
+}
+// pos[item] = rank within its graph; jump/max init for the cycle search
+__global__ void k_minit(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG, int n_items,
+                        const uint64_t *__restrict__ sorted_items, const int *__restrict__ partner,
+                        int *__restrict__ pos, int *__restrict__ jump, int *__restrict__ mx,
+                        int *__restrict__ oncyc) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_items; q += gridDim.x * blockDim.x) {
+        const int i = (int)sorted_items[q];
+        const int g = find_graph(bstart, nG, i);
+        const GDev &d = G[g];
+        int p = partner[d.boff + (i - bstart[g])];
+        if (p >= d.C) p = -1;  // out-of-range partners count as none
+        pos[i] = q - bstart[g];
+        jump[i] = p >= 0 ? bstart[g] + p : i;
+        mx[i] = p >= 0 ? q - bstart[g] : -1;
+        oncyc[i] = 0;
+    }
+}
+__global__ void k_mdouble(int n_items, const int *__restrict__ j0, const int *__restrict__ m0, int *__restrict__ j1,
+                          int *__restrict__ m1) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) {
+        const int a = j0[i];
+        j1[i] = j0[a];
+        if (m0) m1[i] = max(m0[i], m0[a]);
+    }
+}
+__global__ void k_mmark(int n_items, const int *__restrict__ jump, int *__restrict__ oncyc) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) oncyc[jump[i]] = 1;
+}
+// flag in sorted order: valid partner and not the closing edge of a cycle
+__global__ void k_mflags(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG, int n_items,
+                         const uint64_t *__restrict__ sorted_items, const int *__restrict__ partner,
+                         const int *__restrict__ pos, const int *__restrict__ mx, const int *__restrict__ oncyc,
+                         int *__restrict__ flag) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_items; q += gridDim.x * blockDim.x) {
+        const int i = (int)sorted_items[q];
+        const int g = find_graph(bstart, nG, i);
+        const GDev &d = G[g];
+        const int p = partner[d.boff + (i - bstart[g])];
+        const bool valid = p >= 0 && p < d.C;
+        const bool closes = oncyc[i] && pos[i] == mx[i];
+        flag[q] = (valid && !closes) ? 1 : 0;
+    }
+}
+// accepted edges: the first `merges` flagged candidates of each graph
+__global__ void k_maccept(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG, int n_items,
+                          const uint64_t *__restrict__ sorted_items, const int *__restrict__ partner,
+                          const int *__restrict__ flag, const long long *__restrict__ ex, int *__restrict__ jump) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_items; q += gridDim.x * blockDim.x) {
+        const int i = (int)sorted_items[q];
+        const int g = find_graph(bstart, nG, i);
+        const GDev &d = G[g];
+        const long long before = ex[q] - ex[bstart[g]];
+        const bool acc = flag[q] && before < d.merges;
+        jump[i] = acc ? bstart[g] + partner[d.boff + (i - bstart[g])] : i;
+    }
+}
+__global__ void k_mlow_init(int n_items, int *__restrict__ low) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) low[i] = 0x7fffffff;
+}
+__global__ void k_mlow(int n_items, const int *__restrict__ root, int *__restrict__ low) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x)
+        atomicMin(&low[root[i]], i);
+}
+__global__ void k_mrep(int n_items, const int *__restrict__ root, const int *__restrict__ low, int *__restrict__ rep) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x)
+        rep[i] = (low[root[i]] == i) ? 1 : 0;
+}
+// map[item] = new local label; per-graph new block count
+__global__ void k_mmap(const int *__restrict__ bstart, int nG, int n_items, const int *__restrict__ root,
+                       const int *__restrict__ low, const long long *__restrict__ ex, int *__restrict__ map) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(bstart, nG, i);
+        map[i] = (int)(ex[low[root[i]]] - ex[bstart[g]]);
+    }
+}
+// per-graph count of flagged items (exclusive scan ex with total at ex[n_items])
+__global__ void k_group_counts(const int *__restrict__ bstart, int nG, int n_items, const long long *__restrict__ ex,
+                               int *__restrict__ gC) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nG) return;
+    const int lo = bstart[g], hi = g + 1 < nG ? bstart[g + 1] : n_items;
+    gC[g] = (int)(ex[hi] - ex[lo]);
+}
+// lab <- map[blkstart[g] + lab] over the vertex items
+__global__ void k_relabel(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG, int n_vitems,
+                          const int *__restrict__ blkstart, const int *__restrict__ map) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_vitems; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(vstart, nG, i);
+        const GDev &d = G[g];
+        const int v = i - vstart[g];
+        d.lab[v] = map[blkstart[g] + d.lab[v]];
+    }
+}
+// compaction: occupied labels
+__global__ void k_occupied(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG, int n_vitems,
+                           const int *__restrict__ blkstart, int *__restrict__ occ) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_vitems; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(vstart, nG, i);
+        const GDev &d = G[g];
+        occ[blkstart[g] + d.lab[i - vstart[g]]] = 1;
+    }
+}
+__global__ void k_compact_map(const int *__restrict__ bstart, int nG, int n_items, const long long *__restrict__ ex,
+                              int *__restrict__ map) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) {
+        const int g = find_graph(bstart, nG, i);
+        map[i] = (int)(ex[i] - ex[bstart[g]]);
+    }
+}
+
+}  // namespace
+
+size_t hub_scratch_ints_per_slot() { return HUB_SLOT_INTS; }
+int dl_chunks_of(int e, int C) { return (e + DL_CHUNK - 1) / DL_CHUNK + (2 * C + DL_CHUNK - 1) / DL_CHUNK; }
+
+// ---------------------------------------------------------------- host launchers
+int build_union_sparse(const GDev *dG, const StepMeta &m, SparseBM &bm, UnionScratch &ws, hipStream_t s) {
+    const long long Etot = m.Etot;
+    const int Ctot = m.Ctot;
+    bm.Ctot = Ctot;
+    int rc;
+    // 1. one key per edge: (block of source) * Ctot + block of target, sorted
+    hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G, (int)m.Ntot,
+                       Ctot, ws.k0);
+    SBP_LAUNCH_CHECK();
+    if ((rc = radix_sort(ws.k0, ws.k1, nullptr, nullptr, Etot, ceil_log2((uint64_t)Ctot * (uint64_t)Ctot), ws.temp, s)))
+        return rc;
+    // 2. run-length encode into the row lists
+    int *flags = ws.i0, *urow = ws.i1, *start = bm.crow;  // crow is free until step 3
+    hipLaunchKernelGGL(k_rle_flags, dim3(grid_for(Etot, BLK, 8192)), dim3(BLK), 0, s, ws.k0, Etot, flags);
+    SBP_LAUNCH_CHECK();
+    if ((rc = scan_exclusive_i32(flags, ws.s0, Etot, bm.nnz, ws.temp, s))) return rc;
+    hipLaunchKernelGGL(k_rle_emit, dim3(grid_for(Etot, BLK, 8192)), dim3(BLK), 0, s, ws.k0, flags, ws.s0, Etot, Ctot,
+                       urow, bm.rcol, start);
+    hipLaunchKernelGGL(k_rle_count, dim3(grid_for(Etot, BLK, 8192)), dim3(BLK), 0, s, start, bm.nnz, Etot, bm.rval);
+    hipLaunchKernelGGL(k_lower_bounds, dim3(grid_for(Ctot + 1, BLK, 8192)), dim3(BLK), 0, s, urow, bm.nnz, Ctot,
+                       bm.rptr);
+    SBP_LAUNCH_CHECK();
+    // 3. columns: stable sort of the entries by column (padding sorts last)
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(Etot, BLK, 8192)), dim3(BLK), 0, s, urow, bm.rcol, bm.rval, bm.nnz,
+                       Etot, Ctot, ws.k0, ws.v0);
+    SBP_LAUNCH_CHECK();
+    if ((rc = radix_sort(ws.k0, ws.k1, ws.v0, ws.v1, Etot, ceil_log2((uint64_t)Ctot + 1), ws.temp, s))) return rc;
+    int *ccol = ws.i0;
+    hipLaunchKernelGGL(k_csc_emit, dim3(grid_for(Etot, BLK, 8192)), dim3(BLK), 0, s, ws.k0, ws.v0, bm.nnz, ccol,
+                       bm.crow, bm.cval);
+    hipLaunchKernelGGL(k_lower_bounds, dim3(grid_for(Ctot + 1, BLK, 8192)), dim3(BLK), 0, s, ccol, bm.nnz, Ctot,
+                       bm.cptr);
+    SBP_LAUNCH_CHECK();
+    // 4. degrees and proposal tables, wave per block
+    hipLaunchKernelGGL(k_block_rows, dim3(grid_for((long long)Ctot * 64, BLK, 8192)), dim3(BLK), 0, s, bm);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_dl(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch &ws, hipStream_t s) {
+    if (m.n_chunks > 0)
+        hipLaunchKernelGGL(k_dl_partial, dim3(m.n_chunks), dim3(BLK), 0, s, dG, m.chstart, m.G, m.n_chunks, bm,
+                           ws.dl_part);
+    hipLaunchKernelGGL(k_dl_final, dim3((m.G + 63) / 64), dim3(64), 0, s, dG, m.chstart, m.G, m.n_chunks, ws.dl_part,
+                       ws.dl);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch &ws, const SweepTraceDev &tr,
+                hipStream_t s) {
+    {
+    ProfileScope prof("sweep_eval", s);
+    if (m.n_leaf > 0) {
+        hipLaunchKernelGGL(k_sweep_leaf, dim3(grid_for(m.n_leaf, LEAF_WAVES, 16384)), dim3(LEAF_WAVES * 64), 0, s, dG,
+                           m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
+        SBP_LAUNCH_CHECK();
+    }
+    if (m.n_hub > 0) {
+        const int grid = m.n_hub < ws.hub_slots ? m.n_hub : ws.hub_slots;
+        hipLaunchKernelGGL(k_sweep_hub, dim3(grid), dim3(HUB_THREADS), 0, s, dG, m.hub, m.G, m.n_hub, bm, ws.nb, tr,
+                           ws.hub_scratch);
+        SBP_LAUNCH_CHECK();
+    }
+    }
+    hipLaunchKernelGGL(k_sweep_apply, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G,
+                       (int)m.Ntot, ws.nb);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_merge_scores(const GDev *dG, const StepMeta &m, const SparseBM &bm, int *partner, double *dS, double *dSl,
+                       hipStream_t s) {
+    if (m.n_mblk <= 0) return 0;
+    hipLaunchKernelGGL(k_merge_scores, dim3(grid_for((long long)m.n_mblk * 64, BLK, 16384)), dim3(BLK), 0, s, dG,
+                       m.mblk, m.G, m.n_mblk, bm, partner, dS, dSl);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_merge_apply(const GDev *dG, const StepMeta &m, const int *partner, const double *dSl, UnionScratch &ws,
+                      hipStream_t s) {
+    const int n = m.n_mblk;
+    if (n <= 0) return 0;
+    const int grid = grid_for(n, BLK, 8192);
+    const int G = m.G;
+    const int *bstart = m.mblk;
+    int rc;
+    // order by (rank of dS_local, block): sort by rank, then stably by graph
+    hipLaunchKernelGGL(k_mkeys, dim3(grid), dim3(BLK), 0, s, dG, bstart, G, n, dSl, ws.k0, ws.v0);
+    SBP_LAUNCH_CHECK();
+    if ((rc = radix_sort(ws.k0, ws.k1, ws.v0, ws.v1, n, 64, ws.temp, s))) return rc;
+    if (G > 1) {
+        hipLaunchKernelGGL(k_mgraph_keys, dim3(grid), dim3(BLK), 0, s, bstart, G, n, ws.v0, ws.k0);
+        SBP_LAUNCH_CHECK();
+        if ((rc = radix_sort(ws.k0, ws.k1, ws.v0, ws.v1, n, ceil_log2((uint64_t)G), ws.temp, s))) return rc;
+    }
+    const uint64_t *sorted = ws.v0;
+    int *j0 = ws.mj0, *j1 = ws.mj1, *m0 = ws.mm0, *m1 = ws.mm1;
+    hipLaunchKernelGGL(k_minit, dim3(grid), dim3(BLK), 0, s, dG, bstart, G, n, sorted, partner, ws.mpos, j0, m0,
+                       ws.mcyc);
+    SBP_LAUNCH_CHECK();
+    // the closing edge of each proposal cycle: largest rank on the cycle
+    const int rounds = ceil_log2((uint64_t)(m.maxC_merge > 1 ? m.maxC_merge : 2)) + 1;
+    for (int it = 0; it < rounds; ++it) {
+        hipLaunchKernelGGL(k_mdouble, dim3(grid), dim3(BLK), 0, s, n, j0, m0, j1, m1);
+        int *t = j0; j0 = j1; j1 = t;
+        t = m0; m0 = m1; m1 = t;
+    }
+    hipLaunchKernelGGL(k_mmark, dim3(grid), dim3(BLK), 0, s, n, j0, ws.mcyc);
+    int *flag = ws.i0;
+    hipLaunchKernelGGL(k_mflags, dim3(grid), dim3(BLK), 0, s, dG, bstart, G, n, sorted, partner, ws.mpos, m0, ws.mcyc,
+                       flag);
+    SBP_LAUNCH_CHECK();
+    if ((rc = scan_exclusive_i32(flag, ws.s0, n, nullptr, ws.temp, s))) return rc;
+    // joins: the first `merges` remaining candidates; groups by pointer jumping
+    hipLaunchKernelGGL(k_maccept, dim3(grid), dim3(BLK), 0, s, dG, bstart, G, n, sorted, partner, flag, ws.s0, j0);
+    for (int it = 0; it < rounds; ++it) {
+        hipLaunchKernelGGL(k_mdouble, dim3(grid), dim3(BLK), 0, s, n, j0, (const int *)nullptr, j1, (int *)nullptr);
+        int *t = j0; j0 = j1; j1 = t;
+    }
+    const int *root = j0;
+    hipLaunchKernelGGL(k_mlow_init, dim3(grid), dim3(BLK), 0, s, n, ws.mlow);
+    hipLaunchKernelGGL(k_mlow, dim3(grid), dim3(BLK), 0, s, n, root, ws.mlow);
+    hipLaunchKernelGGL(k_mrep, dim3(grid), dim3(BLK), 0, s, n, root, ws.mlow, ws.i1);
+    SBP_LAUNCH_CHECK();
+    if ((rc = scan_exclusive_i32(ws.i1, ws.s1, n, ws.s1 + n, ws.temp, s))) return rc;
+    hipLaunchKernelGGL(k_mmap, dim3(grid), dim3(BLK), 0, s, bstart, G, n, root, ws.mlow, ws.s1, ws.mmap);
+    hipLaunchKernelGGL(k_group_counts, dim3((G + 63) / 64), dim3(64), 0, s, bstart, G, n, ws.s1, ws.gC);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream_t s) {
+    const int n = m.n_cblk;
+    if (n <= 0) return 0;
+    int rc;
+    if ((rc = fill_i32(ws.i0, 0, n, s))) return rc;
+    if (m.n_cvtx > 0) {
+        hipLaunchKernelGGL(k_occupied, dim3(grid_for(m.n_cvtx, BLK, 8192)), dim3(BLK), 0, s, dG, m.cvtx, m.G, m.n_cvtx,
+                           m.cblk, ws.i0);
+        SBP_LAUNCH_CHECK();
+    }
+    if ((rc = scan_exclusive_i32(ws.i0, ws.s1, n, ws.s1 + n, ws.temp, s))) return rc;
+    hipLaunchKernelGGL(k_compact_map, dim3(grid_for(n, BLK, 8192)), dim3(BLK), 0, s, m.cblk, m.G, n, ws.s1, ws.mmap);
+    hipLaunchKernelGGL(k_group_counts, dim3((m.G + 63) / 64), dim3(64), 0, s, m.cblk, m.G, n, ws.s1, ws.gC);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_relabel(const GDev *dG, int G, const int *vstart, int n_vitems, const int *blkstart, const int *map,
+                  hipStream_t s) {
+    if (n_vitems <= 0) return 0;
+    hipLaunchKernelGGL(k_relabel, dim3(grid_for(n_vitems, BLK, 8192)), dim3(BLK), 0, s, dG, vstart, G, n_vitems,
+                       blkstart, map);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace sbp

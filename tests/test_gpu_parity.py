@@ -1,0 +1,346 @@
+"""GPU (HIP, gfx950) against the CPU oracle, element by element.
+
+Bar: integer state (block matrix, degrees, labels, proposals, block counts)
+bit-exact; FP64 DL changes within 1e-9 relative (floor of 1 nat); accept
+decisions equal except near ties |margin| < 1e-9, where the oracle adopts
+the GPU's decision and the event is counted.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2305_18663_amd import gen, sbp
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sbp.lib()
+    yield
+
+
+def close(a, b, rtol=RTOL):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.all(np.abs(a - b) <= rtol * np.maximum(np.abs(b), 1.0))
+
+
+GRAPHS = {
+    "plain_1k": lambda: gen.plain_1k(),
+    "multi_selfloops": lambda: gen.random_multigraph(300, 2500, seed=5, self_loops=True),
+    "dcsbm_2k": lambda: gen.dcsbm([400] * 5, 30000, 3.0, seed=9, kmax=300),
+}
+
+
+def check_coo(dg, g, lab, C, bm):
+    got = sbp.sbp_blockmodel_coo(dg, C, bm)
+    ref = O.build_blockmodel(g, lab, C)
+    assert np.array_equal(got["rows"], ref["rows"])
+    assert np.array_equal(got["cols"], ref["cols"])
+    assert np.array_equal(got["vals"], ref["vals"])
+    assert np.array_equal(got["dout"], ref["dout"]) and np.array_equal(got["din"], ref["din"])
+    return ref
+
+
+# ---------------------------------------------------------------- blockmodel + DL
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("C", [1, 7, 45, 64, 65, 300])
+def test_blockmodel_and_dl(name, C):
+    g = GRAPHS[name]()
+    if C > g.n:
+        pytest.skip("C > n")
+    lab0 = gen.initial_labels(g.n, C, seed=C)
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(lab0)
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    ref = check_coo(dg, g, lab0, C, bm)
+    assert close(sbp.sbp_description_length(dg, C, bm), ref["dl"], 1e-12)
+
+
+def test_blockmodel_all_singletons():
+    g = GRAPHS["multi_selfloops"]()
+    dg = sbp.DeviceGraph(g)
+    lab0 = np.arange(g.n, dtype=np.int32)
+    bm = sbp.sbp_build_blockmodel(dg, sbp.labels(lab0), g.n)
+    ref = check_coo(dg, g, lab0, g.n, bm)
+    assert close(sbp.sbp_description_length(dg, g.n, bm), ref["dl"], 1e-12)
+
+
+def test_blockmodel_200k_full_size():
+    g = gen.sweep_200k()
+    lab0 = gen.initial_labels(g.n, 45, seed=2001)
+    dg = sbp.DeviceGraph(g)
+    bm = sbp.sbp_build_blockmodel(dg, sbp.labels(lab0), 45)
+    ref = check_coo(dg, g, lab0, 45, bm)
+    assert close(sbp.sbp_description_length(dg, 45, bm), ref["dl"], 1e-12)
+    # sparse tier at the same size
+    lab1 = gen.initial_labels(g.n, 5000, seed=7)
+    bm1 = sbp.sbp_build_blockmodel(dg, sbp.labels(lab1), 5000)
+    ref1 = check_coo(dg, g, lab1, 5000, bm1)
+    assert close(sbp.sbp_description_length(dg, 5000, bm1), ref1["dl"], 1e-12)
+
+
+# ---------------------------------------------------------------- sweeps
+def sweep_parity(g, lab0, C, seed, sweep, n_batches=1, beta=3.0, eps=1, dg=None):
+    dg = dg or sbp.DeviceGraph(g)
+    lab = sbp.labels(lab0)
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, sweep, beta=beta, eps=eps, n_batches=n_batches)
+    near = np.abs(tr["margin"]) < 1e-9
+    force = np.full(g.n, -1, np.int8)
+    force[near] = tr["accept"][near]
+    ref = O.nodal_sweep(g, lab0, C, seed, sweep, beta=beta, eps=eps, n_batches=n_batches, force=force)
+    assert np.array_equal(tr["prop"], ref["prop"]), "proposals differ"
+    noop = tr["prop"] == lab0
+    assert close(tr["dS"][~noop], ref["dS"][~noop]), "dS differs"
+    assert close(tr["lnH"][~noop], ref["lnH"][~noop]), "lnH differs"
+    assert np.array_equal(tr["accept"], ref["acc"]), "accept decisions differ"
+    new = lab.cpu().numpy()
+    assert np.array_equal(new, ref["lab"]), "labels differ"
+    assert tr["proposals"] == g.n and tr["accepted"] == ref["accepted"]
+    assert tr["self_proposals"] == ref["self_proposals"]
+    assert close([tr["sum_dS"]], [ref["sum_dS"]])
+    refbm = check_coo(dg, g, new, C, bm)
+    assert close([tr["dl_after"]], [refbm["dl"]], 1e-12)
+    return new, int(near.sum()), ref
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("C", [3, 45, 64, 65, 200])
+def test_sweep_parity(name, C):
+    g = GRAPHS[name]()
+    lab0 = gen.initial_labels(g.n, C, seed=C + 1)
+    sweep_parity(g, lab0, C, seed=123, sweep=C)
+
+
+@pytest.mark.parametrize("C", [10, 80])
+@pytest.mark.parametrize("n_batches", [2, 7])
+def test_sweep_batches(C, n_batches):
+    g = GRAPHS["plain_1k"]()
+    lab0 = gen.initial_labels(g.n, C, seed=4)
+    sweep_parity(g, lab0, C, seed=9, sweep=3, n_batches=n_batches)
+
+
+@pytest.mark.parametrize("C", [3, 70])
+def test_sweep_sequential_tiny(C):
+    g = gen.random_multigraph(90, 400, seed=3, self_loops=True)
+    lab0 = gen.initial_labels(g.n, C, seed=2)
+    sweep_parity(g, lab0, C, seed=5, sweep=0, n_batches=g.n, beta=1.0)
+
+
+def test_sweep_eps_and_beta():
+    g = GRAPHS["plain_1k"]()
+    lab0 = gen.initial_labels(g.n, 12, seed=1)
+    sweep_parity(g, lab0, 12, seed=8, sweep=1, beta=1.0, eps=0)
+    sweep_parity(g, lab0, 12, seed=8, sweep=2, beta=10.0, eps=3)
+
+
+def test_sweep_isolated_vertices():
+    g = gen.from_edges(50, [0, 1, 2, 3], [1, 2, 3, 0])  # 46 isolated vertices
+    for C in (4, 70 if False else 49):
+        lab0 = gen.initial_labels(g.n, C, seed=C)
+        sweep_parity(g, lab0, C, seed=2, sweep=0)
+
+
+def test_sweeps_200k_full_size():
+    # the measured workload: 200k vertices, 45 blocks, consecutive sweeps
+    g = gen.sweep_200k()
+    lab0 = gen.initial_labels(g.n, 45, seed=2001)
+    dg = sbp.DeviceGraph(g)
+    lab = lab0
+    ties = 0
+    for k in range(2):
+        lab, near, _ = sweep_parity(g, lab, 45, seed=2001, sweep=k, dg=dg)
+        ties += near
+    print(f"near ties logged: {ties}")
+
+
+def test_sweep_200k_sparse_tier():
+    g = gen.sweep_200k()
+    lab0 = gen.initial_labels(g.n, 500, seed=3)
+    sweep_parity(g, lab0, 500, seed=17, sweep=0)
+
+
+# ---------------------------------------------------------------- merges
+def merge_parity(g, lab0, C, seed, phase, x=10, eps=1):
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(lab0)
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    partner, dS, dSl = sbp.sbp_merge_scores(dg, lab, C, bm, seed, phase, proposals=x, eps=eps)
+    rp, rdS, rdSl = O.merge_scores(g, lab0, C, seed, phase, x=x, eps=eps)
+    ties = 0
+    for c in np.nonzero(partner != rp)[0]:
+        # only a near tie of two candidates' scores (keys 2^-20 apart) may differ
+        a = O.merge_delta(g, lab0, C, c, partner[c])[1]
+        b = O.merge_delta(g, lab0, C, c, rp[c])[1]
+        assert abs(math.floor(a * 2**20) - math.floor(b * 2**20)) <= 1, (c, partner[c], rp[c], a, b)
+        ties += 1
+    same = partner == rp
+    assert close(dS[same & (rp >= 0)], rdS[same & (rp >= 0)])
+    assert close(dSl[same & (rp >= 0)], rdSl[same & (rp >= 0)])
+    assert np.all(np.isinf(dS[rp < 0]))
+    return partner, dSl, ties
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("C", [2, 20, 64, 65, 400])
+def test_merge_scores(name, C):
+    g = GRAPHS[name]()
+    if C > g.n:
+        pytest.skip("C > n")
+    lab0 = gen.initial_labels(g.n, C, seed=C + 7)
+    merge_parity(g, lab0, C, seed=31, phase=C)
+
+
+def test_merge_scores_singletons():
+    g = GRAPHS["plain_1k"]()
+    merge_parity(g, np.arange(g.n, dtype=np.int32), g.n, seed=2000, phase=0)
+
+
+def test_merge_scores_with_empty_blocks():
+    g = GRAPHS["plain_1k"]()
+    lab0 = gen.initial_labels(g.n, 50, seed=1) * 2  # odd labels empty, C = 100
+    merge_parity(g, lab0.astype(np.int32), 100, seed=5, phase=1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_merge_apply_random(seed):
+    rng = np.random.default_rng(seed)
+    C = int(rng.integers(2, 3000))
+    partner = rng.integers(-1, C, C).astype(np.int32)
+    partner[partner == np.arange(C)] = -1
+    dSl = np.round(rng.normal(size=C) * 4, 1)  # many exact ties
+    dSl[partner < 0] = np.inf
+    for m in (0, 1, C // 3, C // 2, C):
+        got = sbp.sbp_merge_apply(partner, dSl, m)
+        ref = O.merge_apply(partner, dSl, m)
+        assert got[0] == ref[0]
+        assert np.array_equal(got[1], ref[1])
+
+
+def test_merge_apply_cycles_and_chains():
+    C = 12
+    partner = np.array([1, 2, 0, 4, 5, 3, 7, 6, -1, 8, 9, 10], np.int32)
+    dSl = np.array([.3, .1, .2, .5, .4, .6, .7, .7, np.inf, .2, .2, .2])
+    for m in range(C + 1):
+        got = sbp.sbp_merge_apply(partner, dSl, m)
+        ref = O.merge_apply(partner, dSl, m)
+        assert got[0] == ref[0] and np.array_equal(got[1], ref[1]), m
+
+
+def test_compact():
+    rng = np.random.default_rng(3)
+    for C in (1, 5, 300, 5000):
+        lab0 = rng.integers(0, C, 4000).astype(np.int32)
+        lab = sbp.labels(lab0)
+        k = sbp.sbp_compact(lab, C)
+        rk, rlab = O.compact(lab0, C)
+        assert k == rk and np.array_equal(lab.cpu().numpy(), rlab)
+
+
+# ---------------------------------------------------------------- whole method
+def partition_parity(g, **kw):
+    dg = sbp.DeviceGraph(g)
+    res = sbp.sbp_partition(dg, **kw)
+    ora = O.partition(g, **kw)
+    assert np.array_equal(res["trace"], ora["trace"]), (res["trace"], ora["trace"])
+    assert close(res["trace_dl"], ora["trace_dl"])
+    assert res["C"] == ora["C"]
+    assert np.array_equal(res["lab"], ora["lab"])
+    assert close([res["dl"]], [ora["dl"]])
+    return res
+
+
+def test_partition_tiny_two_cliques():
+    src, dst = [], []
+    for blk in (range(0, 4), range(4, 8)):
+        for u in blk:
+            for w in blk:
+                if u != w:
+                    src += [u] * 3
+                    dst += [w] * 3
+    g = gen.from_edges(8, src + [0, 5], dst + [5, 0])
+    res = partition_parity(g, seed=7)
+    assert res["C"] == 2
+
+
+def test_partition_single_vertex_and_edgeless():
+    partition_parity(gen.from_edges(1, [], []), seed=1)
+    partition_parity(gen.from_edges(6, [], []), seed=1)
+
+
+def test_partition_1k():
+    res = partition_parity(gen.plain_1k(), seed=2000)
+    assert 5 <= res["C"] <= 20
+
+
+def test_partition_easy_planted():
+    g = gen.dcsbm([100] * 6, 12000, 5.0, seed=31, kmin=10, kmax=100)
+    partition_parity(g, seed=12)
+
+
+def test_partition_batches_per_sweep():
+    partition_parity(gen.plain_1k(seed=55), seed=3, n_batches=4)
+
+
+def test_partition_from_given_assignment():
+    g = gen.plain_1k()
+    lab0 = gen.initial_labels(g.n, 80, seed=1)
+    dg = sbp.DeviceGraph(g)
+    res = sbp.sbp_partition(dg, assign_in=sbp.labels(lab0), C_in=80, seed=4)
+    ora = O.partition(g, lab_in=lab0, C_in=80, seed=4)
+    assert res["C"] == ora["C"] and np.array_equal(res["lab"], ora["lab"])
+
+
+# ---------------------------------------------------------------- batched and continuous
+def test_batch_equals_alone():
+    graphs = [gen.batch_graph(n, seed=3000 + i) for i, n in enumerate([500, 1200, 800, 2500, 650])]
+    dgs = [sbp.DeviceGraph(g) for g in graphs]
+    kw = [dict(seed=4000 + i) for i in range(len(graphs))]
+    batch = sbp.sbp_partition_batch(dgs, kw)
+    for i, dg in enumerate(dgs):
+        alone = sbp.sbp_partition(dg, **kw[i])
+        assert batch[i]["C"] == alone["C"]
+        assert np.array_equal(batch[i]["lab"], alone["lab"])
+        assert batch[i]["dl"] == alone["dl"]  # same arithmetic in the same order
+        assert np.array_equal(batch[i]["trace"], alone["trace"])
+
+
+def test_batch_matches_oracle():
+    graphs = [gen.batch_graph(n, seed=3100 + i) for i, n in enumerate([500, 700])]
+    res = sbp.sbp_partition_batch([sbp.DeviceGraph(g) for g in graphs], [dict(seed=7), dict(seed=8)])
+    for i, g in enumerate(graphs):
+        ora = O.partition(g, seed=7 + i)
+        assert res[i]["C"] == ora["C"] and np.array_equal(res[i]["lab"], ora["lab"])
+
+
+def test_engine_continuous_admission():
+    graphs = [gen.batch_graph(n, seed=3200 + i) for i, n in enumerate([600, 900, 500, 1500])]
+    dgs = [sbp.DeviceGraph(g) for g in graphs]
+    alone = [sbp.sbp_partition(dg, seed=50 + i) for i, dg in enumerate(dgs)]
+    V = sum(g.n for g in graphs[:2]) + 100
+    E = sum(g.e for g in graphs[:2]) + 100
+    eng = sbp.Engine(V, E, 3)
+    pending = list(range(len(graphs)))
+    results = {}
+    steps = 0
+    while pending or len(results) < len(graphs):
+        while pending and eng.admit(dgs[pending[0]], pending[0], seed=50 + pending[0]):
+            pending.pop(0)
+        eng.step()
+        steps += 1
+        for tag, C, dl, out in eng.poll():
+            results[tag] = (C, dl, out.cpu().numpy())
+        assert steps < 100000
+    eng.close()
+    for i in range(len(graphs)):
+        C, dl, lab = results[i]
+        assert C == alone[i]["C"] and dl == alone[i]["dl"] and np.array_equal(lab, alone[i]["lab"])
