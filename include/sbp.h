@@ -294,6 +294,13 @@ int sbp_engine_poll(sbp_engine *eng, int64_t *tag, int32_t *C, double *dl);
 size_t sbp_engine_graph_bytes(int32_t n, int32_t e);
 int sbp_engine_destroy(sbp_engine *eng);
 
+/* Launch-shape tuning (results do not depend on it).  Keys:
+ *   "dense_eval_workgroups"  workgroups of the dense sweep-evaluation grid
+ *                            (0 = one per 64-vertex chunk, capped at 4 per CU)
+ *   "dense_delta_workgroups" workgroups of the dense block-matrix update
+ * Returns SBP_E_ARG for an unknown key or a value out of range. */
+int sbp_tune(const char *key, int64_t value);
+
 /* Kernel timing for measurement.  While enabled, HIP events are recorded
  * on the calling stream immediately before and after every launch of the
  * sweep-evaluation kernel ("sweep_eval"; dense and sparse tiers).

@@ -216,6 +216,7 @@ BMView bm_layout(void *base, int n, int e, int C) {
         v.d.din = a.take<int>(C);
         v.d.dl = a.take<double>(1);
         v.delta = a.take<int>((size_t)C * C);
+        v.d.ftab = a.take<double>(SBP_FTAB_N);
         v.dl = v.d.dl;
         v.spare = a.take<long long>(1);
     } else {
@@ -1269,6 +1270,12 @@ int sbp_partition(const sbp_graph *g, const int32_t *assign_in, int32_t C_in, co
     }
     sbp_engine_destroy(eng);
     return rc;
+}
+
+int sbp_tune(const char *key, int64_t value) {
+    if (!key) return fail(SBP_E_ARG, "null key");
+    if (dense_tune(key, (long long)value) == 0) return 0;
+    return fail(SBP_E_ARG, std::string("unknown tuning key or value: ") + key);
 }
 
 int sbp_profile_enable(int32_t on) {

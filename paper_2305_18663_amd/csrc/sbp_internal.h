@@ -148,6 +148,7 @@ struct DenseBM {
     int *cdf;         // [C*C] running sums of e_ts = M_ts + M_st over s
     int *dout, *din;  // [C]
     double *dl;       // [1]
+    double *ftab;     // [SBP_FTAB_N] f(x) = x ln x for small integers
 };
 struct DenseScratch {
     int *delta;             // [C*C] change of M of one batch (kept zero between batches)
@@ -161,5 +162,6 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
                       sbp_sweep_stats_dev *stats, hipStream_t s);
 int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *dS, double *dSl, hipStream_t s);
 int dense_workgroups();
+int dense_tune(const char *key, long long value);
 
 }  // namespace sbp

@@ -102,6 +102,7 @@ _SIGS = {
     "sbp_engine_poll": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32),
                                    ct.POINTER(ct.c_double)]),
     "sbp_engine_destroy": (ct.c_int, [ct.c_void_p]),
+    "sbp_tune": (ct.c_int, [ct.c_char_p, ct.c_int64]),
     "sbp_profile_enable": (ct.c_int, [ct.c_int32]),
     "sbp_profile_read": (ct.c_int, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.c_int32]),
 }
@@ -329,6 +330,11 @@ def sbp_partition_batch(dgs, param_list=None, **kw):
         tr, trdl = sbp_partition_trace(i)
         res.append(dict(lab=outs[i].cpu().numpy(), C=C[i], dl=dl[i], trace=tr, trace_dl=trdl))
     return res
+
+
+def sbp_tune(key, value):
+    """Set a launch-shape tuning knob (results do not depend on it)."""
+    _check(lib().sbp_tune(key.encode(), int(value)))
 
 
 def sbp_profile_enable(on=True):
