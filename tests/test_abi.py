@@ -45,8 +45,9 @@ def test_size_queries():
     L = sbp.lib()
     assert L.sbp_blockmodel_bytes(1000, 8000, 10) > 4 * 100
     dense = L.sbp_blockmodel_bytes(1000, 8000, 64)
-    sparse = L.sbp_blockmodel_bytes(1000, 8000, 65)
-    assert sparse > dense  # the sparse tier stores rows, columns and proposal tables
+    assert dense >= 8 * (1 << 18)  # the dense tier carries the f(x) = x ln x table
+    # the sparse tier stores rows, columns and proposal tables sized by the edges
+    assert L.sbp_blockmodel_bytes(1000, 80000, 65) > L.sbp_blockmodel_bytes(1000, 8000, 65) + 8 * 72000
     assert L.sbp_blockmodel_bytes(0, 10, 1) == 0
     assert L.sbp_engine_workspace_bytes(1000, 8000, 4) > L.sbp_engine_graph_bytes(1000, 8000)
     n = (ct.c_int32 * 2)(100, 200)
