@@ -52,17 +52,128 @@ def cpu_baseline(g, lab0, C, seed, budget_s=15.0, max_sweeps=4):
                       f"(gcc -O2) on {platform.processor() or platform.machine()}, {dt:.1f} s"}
 
 
+def _batch_member(args):
+    from paper_2305_18663_amd import gen
+    n, seed = args
+    return gen.batch_graph(int(n), seed=int(seed))
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_graphs(specs, workers=16):
+    """Seeded graphs generated in fresh (spawned) processes, before any GPU use."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, len(specs))) as pool:
+        return pool.map(_batch_member, specs, chunksize=4)
+
+
+def bench_batch(args):
+    """256 uneven DCSBM graphs: one batched partition vs 256 plain partitions."""
+    import numpy as np
+    from paper_2305_18663_amd import gen
+    sizes = gen.batch_sizes(args.graphs, seed=3000)
+    graphs = make_graphs([(n, 3000 + i) for i, n in enumerate(sizes)])
+    progress(f"generated {len(graphs)} graphs")
+    import torch
+    from paper_2305_18663_amd import sbp
+    torch.cuda.set_device(0)
+    dgs = [sbp.DeviceGraph(g, "cuda:0") for g in graphs]
+    params = [dict(seed=4000 + i) for i in range(len(dgs))]
+    sbp.sbp_partition(dgs[0], **params[0])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batched = sbp.sbp_partition_batch(dgs, params)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    progress(f"batched partition of {len(dgs)} graphs: {t_b:.2f} s")
+    t0 = time.perf_counter()
+    plain = []
+    for i, d in enumerate(dgs):
+        plain.append(sbp.sbp_partition(d, **params[i]))
+        if i % 32 == 31:
+            progress(f"plain partitions: {i + 1}/{len(dgs)}")
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    same = all(b["C"] == p["C"] and b["dl"] == p["dl"] and np.array_equal(b["lab"], p["lab"])
+               for b, p in zip(batched, plain))
+    line = {"metric": "graphs/s, batched vs plain (256 uneven DCSBM graphs)", "value": len(dgs) / t_b,
+            "unit": "graphs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{len(dgs)} directed DCSBM graphs, N lognormal on [500, 50000] (median 5000), "
+                                   f"~sqrt(N) planted blocks, E = 8N, ratio 2.5; whole method from C = N",
+                       "total_vertices": int(sizes.sum()), "total_edges": int(sum(g.e for g in graphs))},
+            "batched_s": t_b, "plain_s": t_p, "plain_graphs_per_s": len(dgs) / t_p, "speedup": t_p / t_b,
+            "identical_results": bool(same),
+            "mean_C": float(np.mean([b["C"] for b in batched]))}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of partition requests at 70% of measured batched capacity."""
+    import numpy as np
+    from paper_2305_18663_amd import gen
+    sizes = gen.request_sizes(args.requests, seed=5001)
+    cal_sizes = gen.request_sizes(args.calibration, seed=5002)
+    graphs = make_graphs([(n, 6000 + j) for j, n in enumerate(sizes)] +
+                         [(n, 9000 + j) for j, n in enumerate(cal_sizes)])
+    req_graphs, cal_graphs = graphs[:len(sizes)], graphs[len(sizes):]
+    import torch
+    from paper_2305_18663_amd import serve
+    torch.cuda.set_device(0)
+    V = 2_000_000
+    E = 8 * V
+    budget = 48 << 30
+    # capacity: the calibration draw all at time 0
+    srv = serve.PartitionServer(budget, V, E, 512)
+    cal = [serve.Request(j, g, 0.0, dict(seed=7000 + j)) for j, g in enumerate(cal_graphs)]
+    srv.run(cal)
+    progress("calibration done")
+    capacity = serve.latency_summary(cal)["graphs_per_s"]
+    rate = 0.7 * capacity
+    rng = np.random.default_rng(5000)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(req_graphs)))
+    reqs = [serve.Request(j, g, float(a), dict(seed=8000 + j)) for j, (g, a) in enumerate(zip(req_graphs, arrivals))]
+    srv.run(reqs)
+    srv.close()
+    progress("batched serving done")
+    batched = serve.latency_summary(reqs)
+    seq = [serve.Request(j, g, float(a), dict(seed=8000 + j)) for j, (g, a) in enumerate(zip(req_graphs, arrivals))]
+    serve.serve_sequential(seq, progress=progress)
+    plain = serve.latency_summary(seq)
+    same = all(a.C == b.C and a.dl == b.dl and np.array_equal(a.labels, b.labels) for a, b in zip(reqs, seq))
+    line = {"metric": "graphs/s and p50/p99 latency, continuous batching vs plain (Poisson requests)",
+            "value": batched["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1, "higher_is_better": True,
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{len(reqs)} requests, N lognormal on [1000, 200000] (median 14142), "
+                                   f"~sqrt(N) planted blocks, E = 8N; Poisson arrivals at 70% of the batched "
+                                   f"capacity measured on {len(cal)} calibration requests",
+                       "arrival_rate_per_s": rate, "capacity_graphs_per_s": capacity,
+                       "hbm_budget_bytes": budget, "engine_vertices": V, "engine_edges": E},
+            "batched": batched, "plain": plain, "identical_results": bool(same)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["sweep", "batch", "serve"], default="sweep")
+    ap.add_argument("--graphs", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--calibration", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               f"(the multi-GPU sharding is a design note, not code)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
