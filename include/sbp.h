@@ -142,8 +142,20 @@ size_t sbp_blockmodel_bytes(int32_t n, int32_t e, int32_t C);
 size_t sbp_workspace_bytes(int32_t op, int32_t n, int32_t e, int32_t C);
 
 /* ------------------------------------------------------------------ */
-/* Graph check (SYNC)                                                  */
+/* Graph ingest and check (SYNC)                                       */
 /* ------------------------------------------------------------------ */
+/* Builds the graph arrays of sbp_graph from a list of e directed edges
+ * (src[i] -> dst[i], device arrays, multi-edges and self-loops allowed):
+ * out_ptr[n+1]/out_idx[e] sorted by (source, target) and in_ptr[n+1]/
+ * in_idx[e] sorted by (target, source), all caller-owned device arrays
+ * (Sec. II-A: the directed graph of V vertices and E edges).  Returns
+ * SBP_E_GRAPH if an endpoint lies outside [0, n), SBP_E_SPACE if the
+ * workspace (sbp_graph_workspace_bytes) is too small. */
+size_t sbp_graph_workspace_bytes(int32_t n, int32_t e);
+int sbp_graph_from_edges(int32_t n, int32_t e, const int32_t *src, const int32_t *dst, int32_t *out_ptr,
+                         int32_t *out_idx, int32_t *in_ptr, int32_t *in_idx, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* Checks monotone pointers, ptr[0] = 0, ptr[n] = e, ids in [0, n), equal
  * edge counts, and the degree limit.  Returns SBP_OK or SBP_E_GRAPH/LIMIT. */
 int sbp_validate_graph(const sbp_graph *g /*[host]*/, void *ws, size_t ws_bytes, void *stream);

@@ -859,6 +859,30 @@ int sbp_validate_graph(const sbp_graph *g, void *ws, size_t ws_bytes, void *stre
     return 0;
 }
 
+size_t sbp_graph_workspace_bytes(int32_t n, int32_t e) {
+    if (n < 1 || e < 0) return 0;
+    return single_layout(nullptr, 0, n, e).bytes;
+}
+
+int sbp_graph_from_edges(int32_t n, int32_t e, const int32_t *src, const int32_t *dst, int32_t *out_ptr,
+                         int32_t *out_idx, int32_t *in_ptr, int32_t *in_idx, void *ws, size_t ws_bytes,
+                         void *stream) {
+    if (n < 1 || e < 0 || !out_ptr || !in_ptr || (e > 0 && (!src || !dst || !out_idx || !in_idx)))
+        return fail(SBP_E_ARG, "bad arguments");
+    if (n >= (1 << 30) || e >= (1 << 30)) return fail(SBP_E_LIMIT, "n and e must be below 2^30");
+    SingleWS w = single_layout(ws, ws_bytes, n, e);
+    if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.u.flags, 0);
+    SBP_LAUNCH_CHECK();
+    int rc = graph_from_edges(n, e, src, dst, out_ptr, out_idx, in_ptr, in_idx, w.u.ws, w.u.bm.nnz, w.u.flags, s);
+    if (rc) return rc;
+    int flag = 0;
+    SBP_HIP_CHECK(hipMemcpyAsync(&flag, w.u.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    SBP_HIP_CHECK(hipStreamSynchronize(s));
+    return flag ? fail(SBP_E_GRAPH, "edge endpoint outside [0, n)") : 0;
+}
+
 int sbp_check_labels(int32_t n, const int32_t *assign, int32_t C, void *ws, size_t ws_bytes, void *stream) {
     if (n < 1 || !assign || C < 1) return fail(SBP_E_ARG, "bad arguments");
     if (!ws || ws_bytes < 256) return fail(SBP_E_SPACE, "workspace too small");

@@ -139,6 +139,8 @@ int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream
 int union_relabel(const GDev *dG, int G, const int *vstart, int n_vitems, const int *blkstart, const int *map,
                   hipStream_t s);
 size_t hub_scratch_ints_per_slot();
+int graph_from_edges(int n, long long e, const int *src, const int *dst, int *out_ptr, int *out_idx, int *in_ptr,
+                     int *in_idx, UnionScratch &ws, long long *count, int *flag, hipStream_t s);
 int dl_chunks_of(int e, int C);
 
 // ---------------------------------------------------------------- dense tier (sbp_dense.hip)

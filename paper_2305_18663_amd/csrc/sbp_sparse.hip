@@ -827,6 +827,29 @@ __global__ void k_compact_map(const int *__restrict__ bstart, int nG, int n_item
     }
 }
 
+// ---------------------------------------------------------------- graph ingest
+// key = a * n + b for edge (a, b); flags an endpoint outside [0, n)
+__global__ void k_edge_pair_keys(const int *__restrict__ a, const int *__restrict__ b, long long e, int n,
+                                 uint64_t *__restrict__ keys, int *__restrict__ flag) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < e; i += (long long)gridDim.x * blockDim.x) {
+        const int x = a[i], y = b[i];
+        if (x < 0 || x >= n || y < 0 || y >= n) {
+            atomicOr(flag, 1);
+            keys[i] = 0;
+        } else {
+            keys[i] = (uint64_t)x * (uint64_t)n + (uint64_t)y;
+        }
+    }
+}
+__global__ void k_split_keys(const uint64_t *__restrict__ keys, long long e, int n, int *__restrict__ hi,
+                             int *__restrict__ lo) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < e; i += (long long)gridDim.x * blockDim.x) {
+        hi[i] = (int)(keys[i] / (uint64_t)n);
+        lo[i] = (int)(keys[i] % (uint64_t)n);
+    }
+}
+__global__ void k_set_count(long long *p, long long v) { *p = v; }
+
 }  // namespace
 
 size_t hub_scratch_ints_per_slot() { return HUB_SLOT_INTS; }
@@ -980,6 +1003,29 @@ int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream
     hipLaunchKernelGGL(k_compact_map, dim3(grid_for(n, BLK, 8192)), dim3(BLK), 0, s, m.cblk, m.G, n, ws.s1, ws.mmap);
     hipLaunchKernelGGL(k_group_counts, dim3((m.G + 63) / 64), dim3(64), 0, s, m.cblk, m.G, n, ws.s1, ws.gC);
     SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+// CSR (sorted by source, then target) and CSC (by target, then source) of an
+// edge list; flag (device) is set to 1 if an endpoint lies outside [0, n).
+int graph_from_edges(int n, long long e, const int *src, const int *dst, int *out_ptr, int *out_idx, int *in_ptr,
+                     int *in_idx, UnionScratch &ws, long long *count, int *flag, hipStream_t s) {
+    const int grid = grid_for(e, BLK, 8192);
+    const int bits = ceil_log2((uint64_t)n * (uint64_t)n);
+    int rc;
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, count, e);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int *a = pass == 0 ? src : dst, *b = pass == 0 ? dst : src;
+        int *ptr = pass == 0 ? out_ptr : in_ptr, *idx = pass == 0 ? out_idx : in_idx;
+        if (e > 0) {
+            hipLaunchKernelGGL(k_edge_pair_keys, dim3(grid), dim3(BLK), 0, s, a, b, e, n, ws.k0, flag);
+            SBP_LAUNCH_CHECK();
+            if ((rc = radix_sort(ws.k0, ws.k1, nullptr, nullptr, e, bits, ws.temp, s))) return rc;
+            hipLaunchKernelGGL(k_split_keys, dim3(grid), dim3(BLK), 0, s, ws.k0, e, n, ws.i0, idx);
+        }
+        hipLaunchKernelGGL(k_lower_bounds, dim3(grid_for(n + 1, BLK, 8192)), dim3(BLK), 0, s, ws.i0, count, n, ptr);
+        SBP_LAUNCH_CHECK();
+    }
     return 0;
 }
 

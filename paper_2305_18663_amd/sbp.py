@@ -68,6 +68,9 @@ _SIGS = {
     "sbp_blockmodel_bytes": (ct.c_size_t, [ct.c_int32, ct.c_int32, ct.c_int32]),
     "sbp_workspace_bytes": (ct.c_size_t, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
     "sbp_validate_graph": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "sbp_graph_workspace_bytes": (ct.c_size_t, [ct.c_int32, ct.c_int32]),
+    "sbp_graph_from_edges": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "sbp_check_labels": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "sbp_build_blockmodel": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t,
                                         ct.c_void_p, ct.c_size_t, ct.c_void_p]),
@@ -170,6 +173,26 @@ def labels(x, device="cuda"):
 
 
 # ------------------------------------------------------------------ graph / labels
+def sbp_graph_from_edges(n, src, dst, device="cuda"):
+    """Device CSR/CSC from an edge list; returns a DeviceGraph built on the GPU."""
+    s = torch.as_tensor(np.ascontiguousarray(src, np.int32)).to(device)
+    d = torch.as_tensor(np.ascontiguousarray(dst, np.int32)).to(device)
+    e = s.numel()
+    out_ptr = torch.empty(n + 1, dtype=torch.int32, device=device)
+    in_ptr = torch.empty_like(out_ptr)
+    out_idx = torch.empty(max(e, 1), dtype=torch.int32, device=device)
+    in_idx = torch.empty_like(out_idx)
+    ws = _buffer(lib().sbp_graph_workspace_bytes(n, e), device)
+    _check(lib().sbp_graph_from_edges(n, e, _ptr(s), _ptr(d), _ptr(out_ptr), _ptr(out_idx), _ptr(in_ptr),
+                                      _ptr(in_idx), _ptr(ws), ws.numel(), _stream()))
+    dg = DeviceGraph.__new__(DeviceGraph)
+    dg.n, dg.e, dg.device = n, e, torch.device(device)
+    dg.out_ptr, dg.out_idx, dg.in_ptr, dg.in_idx = out_ptr, out_idx, in_ptr, in_idx
+    dg.struct = Graph(n, e, out_ptr.data_ptr(), out_idx.data_ptr(), in_ptr.data_ptr(), in_idx.data_ptr())
+    dg._ws = None
+    return dg
+
+
 def sbp_validate_graph(dg: DeviceGraph):
     ws = dg.workspace()
     _check(lib().sbp_validate_graph(ct.byref(dg.struct), _ptr(ws), ws.numel(), _stream()))

@@ -50,6 +50,29 @@ def check_coo(dg, g, lab, C, bm):
     return ref
 
 
+# ---------------------------------------------------------------- graph ingest
+@pytest.mark.parametrize("case", ["multi_selfloops", "plain_1k", "edgeless", "single", "200k"])
+def test_graph_from_edges(case):
+    g = {"multi_selfloops": lambda: gen.random_multigraph(300, 2500, seed=5, self_loops=True),
+         "plain_1k": gen.plain_1k, "edgeless": lambda: gen.from_edges(7, [], []),
+         "single": lambda: gen.from_edges(1, [0, 0], [0, 0]), "200k": gen.sweep_200k}[case]()
+    src, dst = g.edges()
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(g.e)  # any edge order gives the same canonical arrays
+    dg = sbp.sbp_graph_from_edges(g.n, src[perm], dst[perm])
+    assert np.array_equal(dg.out_ptr.cpu().numpy(), g.out_ptr)
+    assert np.array_equal(dg.in_ptr.cpu().numpy(), g.in_ptr)
+    assert np.array_equal(dg.out_idx.cpu().numpy()[: g.e], g.out_idx)
+    assert np.array_equal(dg.in_idx.cpu().numpy()[: g.e], g.in_idx)
+    sbp.sbp_validate_graph(dg)
+
+
+def test_graph_from_edges_rejects_bad_endpoint():
+    with pytest.raises(sbp.SbpError) as ei:
+        sbp.sbp_graph_from_edges(5, [0, 1, 5], [1, 2, 0])
+    assert ei.value.code == -2
+
+
 # ---------------------------------------------------------------- blockmodel + DL
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("C", [1, 7, 45, 64, 65, 300])
