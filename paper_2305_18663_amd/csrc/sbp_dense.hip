@@ -3,21 +3,29 @@
 // With at most 64 blocks a wave64 lane owns one block t.  M (C x C int32,
 // Sec. II-A) and the per-block running sums of e_t. = M_t. + M_.t (the
 // proposal tables) live in global memory and are staged in LDS by every
-// workgroup of a sweep.  One sweep batch is four launches:
-//   eval   -- persistent grid, wave per vertex: neighbour-block histogram in
-//             LDS, Philox proposal, DL change over the changed entries of M and
-//             the block degrees (Eq. 1-2), Hastings term, accept test (Alg. 2),
-//             all against the snapshot taken at the start of the batch;
-//   delta  -- every edge with a moved endpoint moves one count from
-//             (old label, old label) to (new label, new label); the edge is
-//             counted by its source when the source moved, else by its target.
-//             (The per-vertex change vectors used for scoring cannot simply be
-//             added up: two adjacent vertices that move together change their
-//             shared edge's entry once, not twice.)  Workgroup deltas of M in
-//             LDS are flushed with integer atomics, so M does not depend on
-//             thread order;
-//   apply  -- M += delta, labels of accepted vertices;
-//   final  -- block degrees, proposal tables, DL (one workgroup, fixed order).
+// workgroup of a sweep.  The blockmodel also keeps, for every edge end, the
+// block of its far end as one byte (C <= 64 fits), in CSR order, so that a
+// sweep reads its neighbour blocks as a contiguous stream instead of
+// gathering a label per end.  A single-batch sweep is three launches:
+//   eval   -- persistent grid over chunks of vertices: neighbour-block
+//             histograms in LDS from the end bytes, Philox proposal, DL change
+//             over the changed entries of M and the block degrees (Eq. 1-2),
+//             Hastings term, accept test (Alg. 2), all against the snapshot
+//             taken at the start of the sweep; writes the accepted block per
+//             vertex;
+//   update -- walks every edge end once: gathers the far end's decision,
+//             rewrites the end byte, and for every out-edge with a moved
+//             endpoint moves one count of M from (old, old) to (new, new)
+//             (adjacent vertices that move together change their shared
+//             edge's entry once, which is why the per-vertex change vectors
+//             used for scoring cannot simply be added up); applies the labels.
+//             Workgroup deltas of M in LDS are flushed with integer atomics,
+//             so M does not depend on thread order;
+//   final  -- M += delta, block degrees, proposal tables, DL (one workgroup,
+//             fixed order).
+// A sweep of several batches evaluates each batch against the labels (the
+// bytes would go stale within the sweep), walks only the moved vertices for
+// the delta, and recomputes the end bytes once at the end.
 #include <string.h>
 
 #include "sbp_internal.h"
@@ -27,7 +35,6 @@ namespace sbp {
 namespace {
 
 constexpr int DC = SBP_DENSE_MAX_C_DEV;
-constexpr int FTAB_N = SBP_FTAB_N;
 
 __device__ __forceinline__ double model_terms_d(double E, double N, double C) {
     const double c2 = C * C;
@@ -54,57 +61,96 @@ __global__ void __launch_bounds__(256) k_dense_hist(GDev g, int *__restrict__ M)
         if (H[i]) atomicAdd(&M[i], H[i]);
 }
 
-// f(x) = x ln x for every integer 0 <= x < FTAB_N, computed on the device with
-// the same xlogx as the direct evaluation, so a lookup returns the very value
-// a direct evaluation would.
-__global__ void k_ftab(double *__restrict__ tab) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < FTAB_N; i += gridDim.x * blockDim.x)
-        tab[i] = xlogx((double)i);
-}
-__device__ __forceinline__ double fx(const double *__restrict__ tab, int x) {
-    return x < FTAB_N ? tab[x] : xlogx((double)x);
+// Block of the far end of every edge end (0xff for a self-loop), wave per
+// vertex.
+__global__ void __launch_bounds__(256) k_dense_ends(GDev g, DenseBM bm) {
+    const int lane = threadIdx.x & 63;
+    unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < g.n; v += (gridDim.x * blockDim.x) >> 6) {
+        const int o1 = g.out_ptr[v + 1], i1 = g.in_ptr[v + 1];
+        for (int j = g.out_ptr[v] + lane; j < o1; j += 64) {
+            const int u = g.out_idx[j];
+            nlo[j] = u == v ? 0xffu : (unsigned char)g.lab[u];
+        }
+        for (int j = g.in_ptr[v] + lane; j < i1; j += 64) {
+            const int u = g.in_idx[j];
+            nli[j] = u == v ? 0xffu : (unsigned char)g.lab[u];
+        }
+    }
 }
 
-// Degrees, proposal tables and DL from M; sweep totals (one workgroup of 1024).
-__global__ void __launch_bounds__(1024) k_dense_final(GDev g, DenseBM bm, const long long *__restrict__ stats_part,
+// f(x) = x ln x for every count 0 <= x <= e (no entry of M and no block degree
+// can exceed the number of edges), computed on the device with the same xlogx
+// as a direct evaluation, so a lookup returns the very value a direct
+// evaluation would.  Lookups clamp the index, so an inconsistent state reads a
+// wrong value instead of out of bounds.
+__global__ void k_ftab(double *__restrict__ tab, unsigned n_max) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i <= (long long)n_max;
+         i += (long long)gridDim.x * blockDim.x)
+        tab[i] = xlogx((double)i);
+}
+__device__ __forceinline__ double fx(const double *__restrict__ tab, unsigned n_max, int x) {
+    return tab[min((unsigned)x, n_max)];
+}
+
+// M += delta (delta cleared), degrees, proposal tables and DL from M; sweep
+// totals.  One workgroup of four waves; a wave scans one row of proposal
+// table at a time (lane b <-> block b).
+constexpr int FIN_T = 256;
+__global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *__restrict__ delta,
+                                                      const long long *__restrict__ stats_part,
                                                       const double *__restrict__ sum_part, int nwg,
                                                       sbp_sweep_stats_dev *__restrict__ stats) {
     __shared__ int Ms[DC * DC];
     __shared__ int so[DC], si[DC];
-    __shared__ double wred[16];
-    __shared__ long long lred[3][16];
-    __shared__ double sred[16];
+    __shared__ double wred[FIN_T / 64], sred[FIN_T / 64];
+    __shared__ long long lred[3][FIN_T / 64];
     const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double *tab = bm.ftab;
-    for (int i = tid; i < CC; i += 1024) Ms[i] = bm.M[i];
-    __syncthreads();
-    if (tid < C) {
-        int x = 0, run = 0;
-        for (int b = 0; b < C; ++b) {
-            x += Ms[tid * C + b];
-            run += Ms[tid * C + b] + Ms[b * C + tid];
-            bm.cdf[tid * C + b] = run;
+    const unsigned fmax = bm.ftab_max;
+    for (int i = tid; i < CC; i += FIN_T) {
+        const int d = delta[i];
+        int m = bm.M[i];
+        if (d) {
+            m += d;
+            bm.M[i] = m;
+            delta[i] = 0;
         }
-        so[tid] = x;
-        bm.dout[tid] = x;
-    } else if (tid >= 64 && tid < 64 + C) {
-        const int t = tid - 64;
-        int x = 0;
-        for (int a = 0; a < C; ++a) x += Ms[a * C + t];
-        si[t] = x;
-        bm.din[t] = x;
+        Ms[i] = m;
+    }
+    __syncthreads();
+    for (int t = wv; t < C; t += FIN_T / 64) {
+        const int mo = lane < C ? Ms[t * C + lane] : 0;  // M_tb
+        const int mi = lane < C ? Ms[lane * C + t] : 0;  // M_bt
+        int run = mo + mi;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(run, o, SBP_WAVE);
+            if (lane >= o) run += y;
+        }
+        if (lane < C) bm.cdf[t * C + lane] = run;
+        const long long dout = wave_sum_i64(mo), din = wave_sum_i64(mi);
+        if (lane == 0) {
+            so[t] = (int)dout;
+            si[t] = (int)din;
+            bm.dout[t] = (int)dout;
+            bm.din[t] = (int)din;
+        }
     }
     __syncthreads();
     // L = sum f(M) - sum f(dout) - sum f(din), fixed order
     double acc = 0.0;
-    for (int i = tid; i < CC; i += 1024) acc += fx(tab, Ms[i]);
-    if (tid < C) acc -= fx(tab, so[tid]);
-    else if (tid >= 64 && tid < 64 + C) acc -= fx(tab, si[tid - 64]);
+    for (int i = tid; i < CC; i += FIN_T) {
+        const double f = fx(tab, fmax, Ms[i]);
+        bm.fM[i] = f;
+        acc += f;
+    }
+    if (tid < C) acc -= fx(tab, fmax, so[tid]) + fx(tab, fmax, si[tid]);
     acc = wave_sum(acc);
     long long a0 = 0, a1 = 0, a2 = 0;
     double sd = 0.0;
     if (stats)
-        for (int w = tid; w < nwg; w += 1024) {
+        for (int w = tid; w < nwg; w += FIN_T) {
             a0 += stats_part[4 * w + 0];
             a1 += stats_part[4 * w + 1];
             a2 += stats_part[4 * w + 2];
@@ -125,7 +171,7 @@ __global__ void __launch_bounds__(1024) k_dense_final(GDev g, DenseBM bm, const 
     if (tid == 0) {
         double L = 0.0, sdt = 0.0;
         long long p = 0, sp = 0, ac = 0;
-        for (int w = 0; w < 16; ++w) {
+        for (int w = 0; w < FIN_T / 64; ++w) {
             L += wred[w];
             p += lred[0][w];
             sp += lred[1][w];
@@ -134,139 +180,178 @@ __global__ void __launch_bounds__(1024) k_dense_final(GDev g, DenseBM bm, const 
         }
         const double dl = model_terms_d((double)g.e, (double)g.n, (double)C) - L;
         bm.dl[0] = dl;
-        if (stats) {
-            stats->proposals += p;
-            stats->self_proposals += sp;
-            stats->accepted += ac;
-            stats->sum_dS_accepted += sdt;
+        if (stats) {  // the first batch of a sweep starts the totals
+            const bool first = g.batch == 0;
+            stats->proposals = (first ? 0 : stats->proposals) + p;
+            stats->self_proposals = (first ? 0 : stats->self_proposals) + sp;
+            stats->accepted = (first ? 0 : stats->accepted) + ac;
+            stats->reserved = first ? 0 : stats->reserved;
+            stats->sum_dS_accepted = (first ? 0.0 : stats->sum_dS_accepted) + sdt;
             stats->dl_after = dl;
         }
     }
 }
 
-template <int GS>
-__device__ __forceinline__ double group_sum(double x) {
-#pragma unroll
-    for (int o = GS / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, SBP_WAVE);
+// Sum over the 16 lanes of a DPP row (a scoring group): four rotate-and-add
+// steps on the VALU, no LDS round trip.  Every lane of the row ends with the
+// sum; lanes may differ in rounding order, so one lane's value is used.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double x) {
+    x += dpp_f64<0x128>(x);  // row_ror:8
+    x += dpp_f64<0x124>(x);  // row_ror:4
+    x += dpp_f64<0x122>(x);  // row_ror:2
+    x += dpp_f64<0x121>(x);  // row_ror:1
     return x;
 }
 
-constexpr int CH = 64;     // vertices per chunk
-constexpr int EVAL_T = 256;  // threads per workgroup
-constexpr int GS = 16;     // lanes per vertex in the scoring phase
-constexpr int UA = 4;      // edge ends in flight per thread in the gather phase
+// Inclusive prefix sum over the 16 lanes of a DPP row.
+__device__ __forceinline__ int row16_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return x;
+}
 
-// Byte offsets of the evaluation kernel's dynamic LDS for C blocks.
-struct EvalOff {
-    int fdo, fdi, inv, W, wst, wsd, Ms, cdf, dsum, dos, dis, H, v, r, op, kout, ip, kin, pre, ell, t0, j0, bytes;
+constexpr int EVAL_T = 256;      // threads per workgroup
+constexpr int GS = 16;           // lanes per vertex in the scoring phase (one DPP row)
+constexpr int NG = EVAL_T / GS;  // scoring groups per workgroup
+constexpr int SEG = 8;           // consecutive edge ends per thread in the histogram phase
+constexpr int LDS_CU = 160 * 1024;
+
+// Arguments of the evaluation kernel: only what it reads, so that the
+// uniform values fit the scalar registers.
+struct EvalArgs {
+    const int *out_ptr, *in_ptr, *out_idx, *in_idx;
+    const int *lab;
+    const int *M, *dout, *din;
+    const double *fM, *ftab;
+    const unsigned char *nlo, *nli;
+    void *nb;
+    long long *stats_part;
+    double *sum_part;
+    unsigned long long seed;
+    double beta;
+    unsigned ftab_max, sweep;
+    int n, C, batch, n_batches, eps, voff;
 };
-__host__ __device__ __forceinline__ int al8(int x) { return (x + 7) & ~7; }
-__host__ __device__ __forceinline__ EvalOff eval_offsets(int C) {
-    EvalOff o;
-    int p = 0;
-    o.fdo = p; p += 8 * C;
-    o.fdi = p; p += 8 * C;
-    o.inv = p; p += 8 * C;
-    o.W = p; p += 8 * 4 * CH;
-    o.wst = p; p += 8 * 3 * (EVAL_T / 64);
-    o.wsd = p; p += 8 * (EVAL_T / 64);
-    o.Ms = p; p += 4 * C * C;
-    o.cdf = p; p += 4 * C * C;
-    o.dsum = p; p += 4 * C;
-    o.dos = p; p += 4 * C;
-    o.dis = p; p += 4 * C;
-    o.H = p; p += 4 * CH * C;
-    o.v = p; p += 4 * CH;
-    o.r = p; p += 4 * CH;
-    o.op = p; p += 4 * CH;
-    o.kout = p; p += 4 * CH;
-    o.ip = p; p += 4 * CH;
-    o.kin = p; p += 4 * CH;
-    o.pre = p; p += 4 * (CH + 1);
-    o.ell = p; p += 4 * CH;
-    o.t0 = p; p += 4 * CH;
-    o.j0 = p; p += 4 * CH;
-    o.bytes = al8(p);
-    return o;
+
+// Static LDS of the evaluation kernel for up to CM blocks: every array sits at
+// a fixed offset.  Rows of M and f(M) are RS = CM + 1 apart (an odd number of
+// words), so a column walk by 16 lanes hits 16 different banks; histogram
+// rows are CM apart.
+template <int CM>
+struct EvalLds {
+    static constexpr int CH = CM >= 48 ? 32 : 48;  // vertices per chunk: four workgroups per CU up to 48 blocks
+    static constexpr int RS = CM + 1;
+    double fM[CM * RS];
+    double fdo[CM], fdi[CM], inv[CM];
+    uint64_t W[3][CH];  // Philox words 1-3 of the chunk's vertices
+    long long wst[3 * (EVAL_T / 64)];
+    double wsd[EVAL_T / 64];
+    int Ms[CM * RS];
+    int dsum[CM], dos[CM], dis[CM];
+    unsigned H[CH * CM];  // out-ends in the low 16 bits, in-ends in the high 16 bits
+    int v[CH], r[CH], op[CH + 1], kout[CH], ip[CH + 1], kin[CH], pre[CH + 1], ell[CH], t0[CH], j0[CH];
+    unsigned char items[NG][CM];
+};
+template <int CM>
+constexpr int eval_chunk() { return EvalLds<CM>::CH; }
+template <int CM>
+constexpr int eval_wgs_per_cu() {
+    return (int)(LDS_CU / sizeof(EvalLds<CM>)) < 4 ? (int)(LDS_CU / sizeof(EvalLds<CM>)) : 4;
 }
 
 // Sweep batch evaluation against the snapshot M.  A workgroup takes CH batch
-// vertices at a time: (0) their pointers, labels and Philox words; (A) every
-// edge end of the chunk in one flattened, balanced loop (coalesced ids, label
-// gathers all in flight) into packed per-vertex block histograms in LDS;
-// (B) groups of GS lanes score GS vertices per round from LDS, lane l of a
-// group owning blocks t = l, l + GS, ...
-__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, int *__restrict__ nb, SweepTraceDev tr,
-                                                      long long *__restrict__ stats_part, double *__restrict__ sum_part) {
-    extern __shared__ __align__(16) char smem[];
-    const EvalOff o = eval_offsets(g.C);
-    struct {
-        double *fdo, *fdi, *inv;
-        uint64_t *W;
-        long long *wst;
-        double *wsd;
-        int *Ms, *cdf, *dsum, *dos, *dis;
-        unsigned *H;
-        int *v, *r, *op, *kout, *ip, *kin, *pre, *ell, *t0, *j0;
-    } L = {(double *)(smem + o.fdo), (double *)(smem + o.fdi), (double *)(smem + o.inv),
-           (uint64_t *)(smem + o.W), (long long *)(smem + o.wst), (double *)(smem + o.wsd),
-           (int *)(smem + o.Ms), (int *)(smem + o.cdf), (int *)(smem + o.dsum), (int *)(smem + o.dos),
-           (int *)(smem + o.dis), (unsigned *)(smem + o.H), (int *)(smem + o.v), (int *)(smem + o.r),
-           (int *)(smem + o.op), (int *)(smem + o.kout), (int *)(smem + o.ip), (int *)(smem + o.kin),
-           (int *)(smem + o.pre), (int *)(smem + o.ell), (int *)(smem + o.t0), (int *)(smem + o.j0)};
-    const double *__restrict__ tab = bm.ftab;
-    const int C = g.C, CC = C * C;
+// vertices at a time:
+//  (0) their pointers, labels and Philox words (wave 0);
+//  (A) every edge end of the chunk into packed per-vertex block histograms in
+//      LDS: a thread takes SEG consecutive ends of the chunk's flattened end
+//      list, finds their owners with one search and a forward walk, issues all
+//      its loads, then counts.  With ENDS the far-end blocks are the stored end
+//      bytes; otherwise (one batch of several) the ids are read and the labels
+//      gathered;
+//  (B) a group of GS lanes (one DPP row) scores one vertex per round: the
+//      proposal from running sums of e_t0. built on the fly from M (exact
+//      integer row scans), the vertex's nonzero blocks t != r, s compacted into
+//      a list, then for every listed block the four changed entries of M --
+//      f of the old values from LDS, f of the new values gathered from the
+//      table, all gathers of the round (and of the 2x2 corner and the block
+//      degrees) in flight together -- the Hastings terms, row sums on DPP and
+//      the three logs of the wave's four vertices in one evaluation.
+// The decision goes to nb: with ENDS one byte per vertex (0xff = stays),
+// otherwise an int (-1 = stays).  TRACE adds the per-vertex record.
+template <bool ENDS, bool TRACE, int CM>
+__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTraceDev tr) {
+    using Lds = EvalLds<CM>;
+    constexpr int CH = Lds::CH;
+    constexpr int RS = Lds::RS;
+    constexpr int NQ = CM / GS;  // blocks per lane in the scoring phase
+    static_assert(CH % NG == 0, "every group scores the same number of vertices per chunk");
+    __shared__ Lds L;
+    const double *__restrict__ tab = a.ftab;
+    const unsigned fmax = a.ftab_max;
+    const int C = a.C;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int grp = tid / GS, gl = tid % GS, wgrp = lane / GS;  // group in workgroup / in wave
-    const double eps = (double)g.eps, epsC = (double)g.eps * (double)C;
-    const long long eC = (long long)g.eps * C;
-    for (int i = tid; i < CC; i += EVAL_T) {
-        L.Ms[i] = bm.M[i];
-        L.cdf[i] = bm.cdf[i];
+    const double eps = (double)a.eps, epsC = (double)a.eps * (double)C;
+    const long long eC = (long long)a.eps * C;
+    for (int i = tid; i < C * C; i += EVAL_T) {
+        const int x = i / C, y = i - x * C;
+        L.Ms[x * RS + y] = a.M[i];
+        L.fM[x * RS + y] = a.fM[i];
     }
     if (tid < C) {
-        const int o = bm.dout[tid], n = bm.din[tid];
+        const int o = a.dout[tid], n = a.din[tid];
         L.dos[tid] = o;
         L.dis[tid] = n;
         L.dsum[tid] = o + n;
-        L.fdo[tid] = fx(tab, o);
-        L.fdi[tid] = fx(tab, n);
+        L.fdo[tid] = fx(tab, fmax, o);
+        L.fdi[tid] = fx(tab, fmax, n);
         L.inv[tid] = 1.0 / ((double)(o + n) + epsC);
     }
     long long n_prop = 0, n_self = 0, n_acc = 0;
     double s_dS = 0.0;
-    const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
+    const int nbc = (a.n - a.batch + a.n_batches - 1) / a.n_batches;
     const int nchunks = (nbc + CH - 1) / CH;
-    const uint32_t k0 = (uint32_t)g.seed, k1 = (uint32_t)(g.seed >> 32);
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         __syncthreads();  // previous chunk done with the LDS
         const int base = chunk * CH;
         const int nv = min(CH, nbc - base);
         // (0) vertex data and words
-        if (tid < CH) {
+        if (tid < 64) {
             int k = 0;
             if (tid < nv) {
-                const int v = g.batch + (base + tid) * g.n_batches;
-                const int op = g.out_ptr[v], ko = g.out_ptr[v + 1] - op;
-                const int ip = g.in_ptr[v], ki = g.in_ptr[v + 1] - ip;
+                const int v = a.batch + (base + tid) * a.n_batches;
+                const int op = a.out_ptr[v], ko = a.out_ptr[v + 1] - op;
+                const int ip = a.in_ptr[v], ki = a.in_ptr[v + 1] - ip;
                 L.v[tid] = v;
-                L.r[tid] = g.lab[v];
+                L.r[tid] = a.lab[v];
                 L.op[tid] = op;
                 L.kout[tid] = ko;
                 L.ip[tid] = ip;
                 L.kin[tid] = ki;
                 k = ko + ki;
                 uint32_t wa[4], wb[4];
-                philox_block((uint32_t)v, g.sweep, 0u, 0u, k0, k1, wa);
-                philox_block((uint32_t)v, g.sweep, 1u, 0u, k0, k1, wb);
+                philox_block((uint32_t)v, a.sweep, 0u, 0u, k0, k1, wa);
+                philox_block((uint32_t)v, a.sweep, 1u, 0u, k0, k1, wb);
                 const uint64_t W0 = (uint64_t)wa[0] | ((uint64_t)wa[1] << 32);
-                L.W[4 * tid + 0] = W0;
-                L.W[4 * tid + 1] = (uint64_t)wa[2] | ((uint64_t)wa[3] << 32);
-                L.W[4 * tid + 2] = (uint64_t)wb[0] | ((uint64_t)wb[1] << 32);
-                L.W[4 * tid + 3] = (uint64_t)wb[2] | ((uint64_t)wb[3] << 32);
+                L.W[0][tid] = (uint64_t)wa[2] | ((uint64_t)wa[3] << 32);
+                L.W[1][tid] = (uint64_t)wb[0] | ((uint64_t)wb[1] << 32);
+                L.W[2][tid] = (uint64_t)wb[2] | ((uint64_t)wb[3] << 32);
                 L.j0[tid] = k > 0 ? (int)draw_idx(W0, (uint64_t)k) : -1;
+                L.ell[tid] = 0;
+                if (tid == nv - 1) {  // ends of the chunk's ranges (consecutive vertices)
+                    L.op[nv] = op + ko;
+                    L.ip[nv] = ip + ki;
+                }
             }
-            L.ell[tid] = 0;
             // exclusive prefix of the edge-end counts (wave 0)
             int x = k;
 #pragma unroll
@@ -274,57 +359,127 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, in
                 const int y = __shfl_up(x, o, SBP_WAVE);
                 if (lane >= o) x += y;
             }
-            L.pre[tid + 1] = x;
+            if (tid < CH) L.pre[tid + 1] = x;
             if (tid == 0) L.pre[0] = 0;
         }
-        for (int i = tid; i < CH * C; i += EVAL_T) L.H[i] = 0;
+        for (int i = tid; i < CH * CM; i += EVAL_T) L.H[i] = 0;
         __syncthreads();
-        // (A) all edge ends of the chunk, UA at a time per thread with every
-        // load issued before its use
-        const int total = L.pre[nv];
-        for (int f0 = tid; f0 < total; f0 += EVAL_T * UA) {
-            int vi[UA], j[UA], u[UA];
+        if constexpr (ENDS) {
+            // (A) histograms from the end bytes: the chunk's vertices are
+            // consecutive, so its out-end bytes form one range and its in-end
+            // bytes another; a thread takes an 8-aligned block of a range
+            // (one 8-byte load; the byte arrays are padded), finds the owner of
+            // its first position and walks forward
+            const int o0 = L.op[0], o1 = L.op[nv], i0 = L.ip[0], i1 = L.ip[nv];
+            const int bo0 = o0 >> 3, nbo = o1 > o0 ? ((o1 + 7) >> 3) - bo0 : 0;
+            const int bi0 = i0 >> 3, nbi = i1 > i0 ? ((i1 + 7) >> 3) - bi0 : 0;
+            for (int rr = tid; rr < nbo + nbi; rr += EVAL_T) {
+                const bool out = rr < nbo;
+                const int p0 = (out ? bo0 + rr : bi0 + (rr - nbo)) * 8;
+                const int lo = out ? o0 : i0, hi = out ? o1 : i1;
+                const uint2 bw = *(const uint2 *)((out ? a.nlo : a.nli) + p0);
+                const int *P = out ? L.op : L.ip;
+                const int pf = max(lo, p0);
+                int l = 0, h = nv - 1;  // owner of pf: last vertex whose range starts at or before it
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (P[mid] <= pf) l = mid; else h = mid - 1;
+                }
+                int w = l, beg = P[l], nxt = P[l + 1];
 #pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                const int f = f0 + q * EVAL_T;
-                int lo = 0, hi = nv - 1;  // last vertex with pre <= f
+                for (int q = 0; q < 8; ++q) {
+                    const int p = p0 + q;
+                    if (p < lo || p >= hi) continue;
+                    while (p >= nxt) {
+                        ++w;
+                        beg = nxt;
+                        nxt = P[w + 1];
+                    }
+                    const unsigned b = ((q < 4 ? bw.x : bw.y) >> (8 * (q & 3))) & 0xffu;
+                    const int j = out ? p - beg : L.kout[w] + (p - beg);
+                    int tt;
+                    if (b == 0xffu) {  // self-loop end
+                        tt = L.r[w];
+                        if (out) atomicAdd(&L.ell[w], 1);
+                    } else {
+                        tt = (int)b;
+                        atomicAdd(&L.H[w * CM + tt], out ? 1u : 65536u);
+                    }
+                    if (j == L.j0[w]) L.t0[w] = tt;
+                }
+            }
+        } else {
+            // (A) histograms: end f of the chunk is end f - pre[w] of its owner w,
+            // out-ends before in-ends
+            const int total = L.pre[nv];
+            for (int f0 = tid * SEG; f0 < total; f0 += EVAL_T * SEG) {
+                int lo = 0, hi = nv - 1;  // owner of f0: last vertex with pre <= f0
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (L.pre[mid] <= f) lo = mid; else hi = mid - 1;
+                    if (L.pre[mid] <= f0) lo = mid; else hi = mid - 1;
                 }
-                vi[q] = f < total ? lo : -1;
-                j[q] = f - L.pre[lo];
-            }
+                int w = lo, beg = L.pre[lo], nxt = L.pre[lo + 1];
+                int wko = L.kout[lo], wop = L.op[lo], wip = L.ip[lo];
+                int wq[SEG], jq[SEG], pq[SEG];
+                unsigned outm = 0;
 #pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                u[q] = -1;
-                if (vi[q] >= 0) {
-                    const int ko = L.kout[vi[q]];
-                    u[q] = j[q] < ko ? g.out_idx[L.op[vi[q]] + j[q]] : g.in_idx[L.ip[vi[q]] + (j[q] - ko)];
+                for (int q = 0; q < SEG; ++q) {
+                    const int f = f0 + q;
+                    if (f < total) {
+                        while (f >= nxt) {
+                            ++w;
+                            beg = nxt;
+                            nxt = L.pre[w + 1];
+                            wko = L.kout[w];
+                            wop = L.op[w];
+                            wip = L.ip[w];
+                        }
+                    }
+                    const int j = f - beg;
+                    const bool out = j < wko;
+                    wq[q] = f < total ? w : -1;
+                    jq[q] = j;
+                    pq[q] = out ? wop + j : wip + (j - wko);
+                    outm |= (out ? 1u : 0u) << q;
                 }
-            }
-            int t[UA];
+                unsigned b[SEG];
+                if constexpr (ENDS) {
 #pragma unroll
-            for (int q = 0; q < UA; ++q) t[q] = (vi[q] >= 0 && u[q] != L.v[vi[q]]) ? g.lab[u[q]] : -1;
-#pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                if (vi[q] < 0) continue;
-                const bool out = j[q] < L.kout[vi[q]];
-                int tt = t[q];
-                if (tt < 0) {  // self-loop end
-                    tt = L.r[vi[q]];
-                    if (out) atomicAdd(&L.ell[vi[q]], 1);
+                    for (int q = 0; q < SEG; ++q)
+                        b[q] = wq[q] >= 0 ? ((outm >> q) & 1u ? a.nlo[pq[q]] : a.nli[pq[q]]) : 0xffu;
                 } else {
-                    atomicAdd(&L.H[vi[q] * C + tt], out ? 1u : 65536u);
+                    int u[SEG];
+#pragma unroll
+                    for (int q = 0; q < SEG; ++q)
+                        u[q] = wq[q] >= 0 ? ((outm >> q) & 1u ? a.out_idx[pq[q]] : a.in_idx[pq[q]]) : 0;
+#pragma unroll
+                    for (int q = 0; q < SEG; ++q)
+                        b[q] = (wq[q] >= 0 && u[q] != L.v[wq[q]]) ? (unsigned)a.lab[u[q]] : 0xffu;
                 }
-                if (j[q] == L.j0[vi[q]]) L.t0[vi[q]] = tt;
+#pragma unroll
+                for (int q = 0; q < SEG; ++q) {
+                    if (wq[q] < 0) break;
+                    const int ww = wq[q];
+                    const bool out = (outm >> q) & 1u;
+                    int tt;
+                    if (b[q] == 0xffu) {  // self-loop end
+                        tt = L.r[ww];
+                        if (out) atomicAdd(&L.ell[ww], 1);
+                    } else {
+                        tt = (int)b[q];
+                        atomicAdd(&L.H[ww * CM + tt], out ? 1u : 65536u);
+                    }
+                    if (jq[q] == L.j0[ww]) L.t0[ww] = tt;
+                }
             }
         }
         __syncthreads();
-        // (B) scoring, GS vertices per round (64/GS per wave)
-        for (int vi = grp; vi < CH; vi += EVAL_T / GS) {
+        // (B) scoring, one vertex per group per round; every group runs the
+        // same number of rounds, so DPP and ballots see whole rows
+        const unsigned below = (1u << gl) - 1u;
+        for (int vi = grp; vi < CH; vi += NG) {
             const bool valid = vi < nv;
-            int v = 0, r = 0, kout = 0, kin = 0, ell = 0;
+            int v = 0, r = 0, kout = 0, kin = 0, ell = 0, t0 = 0;
             uint64_t W1 = 0, W2 = 0, W3 = 0;
             if (valid) {
                 v = L.v[vi];
@@ -332,80 +487,115 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, in
                 kout = L.kout[vi];
                 kin = L.kin[vi];
                 ell = L.ell[vi];
-                W1 = L.W[4 * vi + 1];
-                W2 = L.W[4 * vi + 2];
-                W3 = L.W[4 * vi + 3];
+                t0 = L.t0[vi];
+                W1 = L.W[0][vi];
+                W2 = L.W[1][vi];
+                W3 = L.W[2][vi];
             }
             const int k = kout + kin;
-            const unsigned *Hv = L.H + vi * C;
+            const unsigned *Hv = L.H + vi * CM;
+            // proposal: a uniform block, or the first block b whose running
+            // sum of e_t0,b' = M_t0,b' + M_b',t0 over b' <= b exceeds x
             int s;
-            if (k == 0) {
-                s = (int)draw_idx(W2, (uint64_t)C);
-            } else {
-                const int t0 = L.t0[vi];
-                const long long dt = L.dsum[t0];
-                if (draw_idx(W1, (uint64_t)(dt + eC)) < eC) {
-                    s = (int)draw_idx(W2, (uint64_t)C);
-                } else {
-                    const long long x = draw_idx(W2, (uint64_t)dt);
-                    s = C;
-                    for (int b0 = 0; b0 < C; b0 += GS) {
-                        const int cand = b0 + gl;
-                        const bool hit = cand < C && (long long)L.cdf[t0 * C + cand] > x;
-                        const uint64_t m = (__ballot(hit) >> (wgrp * GS)) & ((1ull << GS) - 1);
-                        if (m && s == C) s = b0 + __builtin_ctzll(m);
-                    }
+            {
+                const long long dt = k > 0 ? (long long)L.dsum[t0] : 0;
+                const bool unif = k == 0 || draw_idx(W1, (uint64_t)(dt + eC)) < (uint64_t)eC;
+                const long long x = unif ? 0 : (long long)draw_idx(W2, (uint64_t)dt);
+                int sp = C;
+                long long carry = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int bb = q * GS + gl;
+                    const int e = (!unif && bb < C) ? L.Ms[t0 * RS + bb] + L.Ms[bb * RS + t0] : 0;
+                    const int run = row16_scan(e);
+                    const bool hit = !unif && bb < C && carry + run > x;
+                    const uint64_t m = (__ballot(hit) >> (wgrp * GS)) & ((1ull << GS) - 1);
+                    if (m && sp == C) sp = q * GS + __builtin_ctzll(m);
+                    carry += __shfl(run, wgrp * GS + GS - 1, SBP_WAVE);
                 }
+                s = unif ? (int)draw_idx(W2, (uint64_t)C) : sp;
             }
             const bool act = valid && s != r;
             if (!act) s = r;  // keeps every index below in range
-            const int *Ms = L.Ms;
+            // blocks t != r, s with a neighbour: a compacted list
+            unsigned char *items = L.items[grp];
+            int n_it = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int t = q * GS + gl;
+                const bool nz = act && t < C && t != r && t != s && Hv[t] != 0u;
+                const unsigned m = (unsigned)(__ballot(nz) >> (wgrp * GS)) & 0xffffu;
+                if (nz) items[n_it + __builtin_popcount(m & below)] = (unsigned char)t;
+                n_it += __builtin_popcount(m);
+            }
+            // the corner item of this lane: entries (lanes 0-3), degrees (4-7)
+            const unsigned hr = Hv[r], hs = Hv[s];
+            const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
+            const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
+            const int c = gl & 3;
+            const int ca = c < 2 ? r : s, cb = (c & 1) ? s : r;  // entry (ca, cb) of the corner
+            const int mdelta = c == 0 ? -ko_r - ki_r - ell : c == 1 ? -ko_s + ki_r : c == 2 ? ko_r - ki_s : ko_s + ki_s + ell;
+            const bool is_m = gl < 4;
+            const int cdeg = c == 0 ? L.dos[r] : c == 1 ? L.dos[s] : c == 2 ? L.dis[r] : L.dis[s];
+            const int ddelta = c == 0 ? -kout : c == 1 ? kout : c == 2 ? -kin : kin;
+            const bool corner = act && gl < 8;
+            const int c_new = is_m ? L.Ms[ca * RS + cb] + mdelta : cdeg + ddelta;
+            const double c_fnew = corner ? fx(tab, fmax, c_new) : 0.0;
+            // listed blocks: four changed entries each, up to NQ per lane, all
+            // table gathers issued before any use
             double dL = 0.0, qf = 0.0, qr = 0.0;
-            // blocks t != r, s: changed entries of rows r, s and columns r, s
-#pragma unroll 2
-            for (int t = gl; t < C; t += GS) {
-                const unsigned h = (act && t != r && t != s) ? Hv[t] : 0u;
-                if (h) {
-                    const int ko = (int)(h & 0xffffu), ki = (int)(h >> 16);
-                    const int rt = r * C + t, st = s * C + t, tr_ = t * C + r, ts = t * C + s;
-                    const int Mrt = Ms[rt], Mst = Ms[st], Mtr = Ms[tr_], Mts = Ms[ts];
-                    // a zero count contributes exactly zero
-                    dL += fx(tab, Mrt - ko) - fx(tab, Mrt) + fx(tab, Mst + ko) - fx(tab, Mst);
-                    dL += fx(tab, Mtr - ki) - fx(tab, Mtr) + fx(tab, Mts + ki) - fx(tab, Mts);
-                    const double kt = (double)(ko + ki);
-                    qf += kt * (((double)(Mts + Mst) + eps) * L.inv[t]);
-                    qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) * L.inv[t]);
+            int ti[NQ];
+            unsigned hq[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = q * GS + gl;
+                ti[q] = i < n_it ? (int)items[i] : -1;
+                hq[q] = ti[q] >= 0 ? Hv[ti[q]] : 0u;
+            }
+            double fn[NQ][4];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int t = ti[q] >= 0 ? ti[q] : 0;
+                const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
+                const int mrt = L.Ms[r * RS + t], mst = L.Ms[s * RS + t];
+                const int mtr = L.Ms[t * RS + r], mts = L.Ms[t * RS + s];
+                fn[q][0] = ko ? fx(tab, fmax, mrt - ko) : 0.0;
+                fn[q][1] = ko ? fx(tab, fmax, mst + ko) : 0.0;
+                fn[q][2] = ki ? fx(tab, fmax, mtr - ki) : 0.0;
+                fn[q][3] = ki ? fx(tab, fmax, mts + ki) : 0.0;
+                if (ti[q] >= 0) {  // Hastings terms while the gathers are in flight
+                    const double kt = (double)(ko + ki), iv = L.inv[t];
+                    qf += kt * (((double)(mts + mst) + eps) * iv);
+                    qr += kt * (((double)(mtr - ki + mrt - ko) + eps) * iv);
                 }
             }
-            // the 2x2 corner (r, s) x (r, s), the four block degrees and the
-            // Hastings terms of t = r and t = s: one item per lane, branch-free
-            {
-                const unsigned hr = Hv[r], hs = Hv[s];
-                const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
-                const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
-                const int Mrr = Ms[r * C + r], Mrs = Ms[r * C + s], Msr = Ms[s * C + r], Mss = Ms[s * C + s];
-                const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
-                const int c = gl & 3;
-                // entries (lanes 0-3) and degrees (lanes 4-7)
-                const int m_old = c == 0 ? Mrr : c == 1 ? Mrs : c == 2 ? Msr : Mss;
-                const int m_d = c == 0 ? drr : c == 1 ? drs : c == 2 ? dsr : dss;
-                const int deg_old = c == 0 ? L.dos[r] : c == 1 ? L.dos[s] : c == 2 ? L.dis[r] : L.dis[s];
-                const int deg_d = c == 0 ? -kout : c == 1 ? kout : c == 2 ? -kin : kin;
-                const bool is_m = gl < 4;
-                const int old = is_m ? m_old : deg_old, nw = old + (is_m ? m_d : deg_d);
-                if (act && gl < 8) dL += (is_m ? 1.0 : -1.0) * (fx(tab, nw) - fx(tab, old));
-                // Hastings terms (lanes 8-11): t = r and t = s before, t = r and t = s after
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (ti[q] < 0) continue;
+                const int t = ti[q];
+                const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
+                if (ko) dL += (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
+                if (ki) dL += (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
+            }
+            if (corner) {
+                const double c_fold = is_m ? L.fM[ca * RS + cb] : (c < 2 ? L.fdo[c == 0 ? r : s] : L.fdi[c == 2 ? r : s]);
+                dL += (is_m ? 1.0 : -1.0) * (c_fnew - c_fold);
+            }
+            // Hastings terms of t = r and t = s (lanes 8-11): before, after
+            if (act && gl >= 8 && gl < 12) {
+                const int Mrr = L.Ms[r * RS + r], Mrs = L.Ms[r * RS + s], Msr = L.Ms[s * RS + r], Mss = L.Ms[s * RS + s];
+                const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s;
                 const int kk = c == 0 ? ko_r + ki_r + 2 * ell : c == 1 ? ko_s + ki_s : c == 2 ? ko_r + ki_r : ko_s + ki_s + 2 * ell;
                 const int num = c == 0 ? Mrs + Msr : c == 1 ? 2 * Mss : c == 2 ? 2 * (Mrr + drr) : Msr + dsr + Mrs + drs;
                 const int den = c == 0 ? L.dsum[r] : c == 1 ? L.dsum[s] : c == 2 ? L.dsum[r] - k : L.dsum[s] + k;
-                if (act && gl >= 8 && gl < 12 && kk) {
+                if (kk) {
                     const double term = (double)kk * (((double)num + eps) / ((double)den + epsC));
                     if (c < 2) qf += term; else qr += term;
                 }
             }
-            dL = group_sum<GS>(dL);
-            qf = group_sum<GS>(qf);
-            qr = group_sum<GS>(qr);
+            dL = row16_sum(dL);
+            qf = row16_sum(qf);
+            qr = row16_sum(qr);
             // the three logs of the wave's 64/GS vertices in one evaluation
             double lg;
             {
@@ -414,16 +604,16 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, in
                 const int src = (q < 64 / GS ? q : 0) * GS;
                 const double xr = __shfl(qr, src, SBP_WAVE), xf = __shfl(qf, src, SBP_WAVE);
                 const double xu = __shfl(u, src, SBP_WAVE);
-                double arg = m == 0 ? xr : m == 1 ? xf : xu;
-                if (!(arg > 0.0)) arg = 1.0;
-                lg = log(arg);
+                // a zero Hastings sum gives -inf, as in a direct evaluation; the
+                // values of vertices that do not move are not used
+                lg = log(m == 0 ? xr : m == 1 ? xf : xu);
             }
             const double lnqr = __shfl(lg, 3 * wgrp + 0, SBP_WAVE);
             const double lnqf = __shfl(lg, 3 * wgrp + 1, SBP_WAVE);
             const double lnu = __shfl(lg, 3 * wgrp + 2, SBP_WAVE);
-            const double dS = -dL;
+            const double dS = -__shfl(dL, wgrp * GS, SBP_WAVE);
             const double lnH = (act && k > 0) ? lnqr - lnqf : 0.0;
-            const double z = -g.beta * dS + lnH;
+            const double z = -a.beta * dS + lnH;
             const bool acc = act && lnu < z;
             if (gl == 0 && valid) {
                 ++n_prop;
@@ -432,14 +622,17 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, in
                     ++n_acc;
                     s_dS += dS;
                 }
-                const int uu = g.voff + v;
-                nb[v] = acc ? s : -1;
-                if (tr.prop) tr.prop[uu] = act ? s : r;
-                if (tr.dS) tr.dS[uu] = act ? dS : 0.0;
-                if (tr.lnH) tr.lnH[uu] = act ? lnH : 0.0;
-                if (tr.margin) tr.margin[uu] = act ? z - lnu : 0.0;
-                if (tr.accept) tr.accept[uu] = acc ? 1 : 0;
-                if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) : -1;
+                if constexpr (ENDS) ((unsigned char *)a.nb)[v] = acc ? (unsigned char)s : 0xffu;
+                else ((int *)a.nb)[v] = acc ? s : -1;
+                if constexpr (TRACE) {
+                    const int uu = a.voff + v;
+                    if (tr.prop) tr.prop[uu] = act ? s : r;
+                    if (tr.dS) tr.dS[uu] = act ? dS : 0.0;
+                    if (tr.lnH) tr.lnH[uu] = act ? lnH : 0.0;
+                    if (tr.margin) tr.margin[uu] = act ? z - lnu : 0.0;
+                    if (tr.accept) tr.accept[uu] = acc ? 1 : 0;
+                    if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) : -1;
+                }
             }
         }
     }
@@ -456,88 +649,119 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(GDev g, DenseBM bm, in
     }
     __syncthreads();
     if (tid == 0) {
-        long long a = 0, b2 = 0, c = 0;
+        long long p = 0, sp = 0, ac = 0;
         double sd = 0.0;
         for (int w = 0; w < EVAL_T / 64; ++w) {
-            a += L.wst[3 * w + 0];
-            b2 += L.wst[3 * w + 1];
-            c += L.wst[3 * w + 2];
+            p += L.wst[3 * w + 0];
+            sp += L.wst[3 * w + 1];
+            ac += L.wst[3 * w + 2];
             sd += L.wsd[w];
         }
-        stats_part[4 * blockIdx.x + 0] = a;
-        stats_part[4 * blockIdx.x + 1] = b2;
-        stats_part[4 * blockIdx.x + 2] = c;
-        stats_part[4 * blockIdx.x + 3] = 0;
-        sum_part[blockIdx.x] = sd;
+        a.stats_part[4 * blockIdx.x + 0] = p;
+        a.stats_part[4 * blockIdx.x + 1] = sp;
+        a.stats_part[4 * blockIdx.x + 2] = ac;
+        a.stats_part[4 * blockIdx.x + 3] = 0;
+        a.sum_part[blockIdx.x] = sd;
     }
 }
 
-// Change of M from the moves of a single-batch sweep, edge-parallel: every
-// out-edge (u, w) whose endpoints' labels changed moves one count from
-// (old u, old w) to (new u, new w).  Chunks of CH vertices per workgroup.
-__global__ void __launch_bounds__(EVAL_T) k_dense_delta_edges(GDev g, const int *__restrict__ nb,
-                                                             int *__restrict__ delta) {
+// After the decisions of a single-batch sweep: every edge end once, chunks of
+// CH consecutive vertices per workgroup.  An out-edge (v, u) moves one count of
+// M from (old v, old u) to (new v, new u) when either endpoint moved (LDS
+// delta, flushed with integer atomics); every end byte takes the far end's new
+// block; the labels of the chunk's vertices take their decisions.  The
+// decisions are read from nb (never from the labels being rewritten), so the
+// workgroups need no ordering.  A thread takes SEG consecutive ends of the
+// chunk (its out-ends, then its in-ends) and issues all their loads and
+// decision gathers before any use.
+constexpr int CHU = 64;  // vertices per chunk of the update
+// A thread takes an 8-aligned block of 8 consecutive end positions of the
+// chunk (its out-ends, then its in-ends): with VEC (16-byte aligned id
+// arrays) the ids come in two 16-byte loads, the end bytes in one 8-byte load
+// (the byte arrays are padded to 256), then the 8 decision gathers.  Bytes
+// outside the chunk are read but neither used nor written: their owners are
+// other workgroups.
+template <bool VEC>
+__global__ void __launch_bounds__(EVAL_T) k_dense_update(GDev g, DenseBM bm, const unsigned char *__restrict__ nb,
+                                                        int *__restrict__ delta) {
     extern __shared__ __align__(16) char smem[];
-    const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63;
+    const int C = g.C, CC = C * C, tid = threadIdx.x;
     int *dl = (int *)smem;
-    int *pre = dl + CC;        // [CH+1]
-    int *op = pre + CH + 1;    // [CH]
-    int *a0 = op + CH;         // old label of the chunk vertex
-    int *a1 = a0 + CH;         // new label
+    int *op = dl + CC;       // [CHU + 1] first out-end; op[nv] = end of the chunk's out-ends
+    int *ip = op + CHU + 1;  // [CHU + 1] first in-end
+    int *a0 = ip + CHU + 1;  // [CHU] old label
+    int *a1 = a0 + CHU;      // [CHU] new label
+    unsigned char *__restrict__ nlo = bm.nl;
+    unsigned char *__restrict__ nli = bm.nl + bm.nl_in;
     for (int i = tid; i < CC; i += EVAL_T) dl[i] = 0;
-    const int nchunks = (g.n + CH - 1) / CH;
+    const int nchunks = (g.n + CHU - 1) / CHU;
     for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         __syncthreads();
-        const int base = chunk * CH, nv = min(CH, g.n - base);
-        if (tid < CH) {
-            int k = 0;
+        const int base = chunk * CHU, nv = min(CHU, g.n - base);
+        if (tid <= nv) {
+            const int v = base + tid;
+            op[tid] = g.out_ptr[v];
+            ip[tid] = g.in_ptr[v];
             if (tid < nv) {
-                const int v = base + tid;
-                const int o = g.out_ptr[v];
-                k = g.out_ptr[v + 1] - o;
-                op[tid] = o;
-                const int old = g.lab[v], x = nb[v];
+                const int old = g.lab[v];
+                const unsigned x = nb[v];
                 a0[tid] = old;
-                a1[tid] = x >= 0 ? x : old;
+                a1[tid] = x != 0xffu ? (int)x : old;
+                if (x != 0xffu) g.lab[v] = (int)x;
             }
-            int x = k;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, SBP_WAVE);
-                if (lane >= o) x += y;
-            }
-            pre[tid + 1] = x;
-            if (tid == 0) pre[0] = 0;
         }
         __syncthreads();
-        const int total = pre[nv];
-        for (int f0 = tid; f0 < total; f0 += EVAL_T * UA) {
-            int vi[UA], w[UA];
+        const int o0 = op[0], o1 = op[nv], i0 = ip[0], i1 = ip[nv];
+        const int bo0 = o0 >> 3, nbo = o1 > o0 ? ((o1 + 7) >> 3) - bo0 : 0;
+        const int bi0 = i0 >> 3, nbi = i1 > i0 ? ((i1 + 7) >> 3) - bi0 : 0;
+        for (int rr = tid; rr < nbo + nbi; rr += EVAL_T) {
+            const bool out = rr < nbo;
+            const int p0 = (out ? bo0 + rr : bi0 + (rr - nbo)) * 8;
+            const int lo = out ? o0 : i0, hi = out ? o1 : i1;
+            const int *__restrict__ idx = out ? g.out_idx : g.in_idx;
+            unsigned char *__restrict__ nlp = out ? nlo : nli;
+            int u[8];
+            if (VEC && p0 + 8 <= g.e) {
+                const int4 A = *(const int4 *)(idx + p0), B = *(const int4 *)(idx + p0 + 4);
+                u[0] = A.x; u[1] = A.y; u[2] = A.z; u[3] = A.w;
+                u[4] = B.x; u[5] = B.y; u[6] = B.z; u[7] = B.w;
+            } else {
 #pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                const int f = f0 + q * EVAL_T;
-                int lo = 0, hi = nv - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (pre[mid] <= f) lo = mid; else hi = mid - 1;
+                for (int q = 0; q < 8; ++q) u[q] = (p0 + q >= lo && p0 + q < hi) ? idx[p0 + q] : 0;
+            }
+            const uint2 bw = *(const uint2 *)(nlp + p0);
+            unsigned b[8], x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool in_run = p0 + q >= lo && p0 + q < hi;
+                b[q] = in_run ? (((q < 4 ? bw.x : bw.y) >> (8 * (q & 3))) & 0xffu) : 0x100u;  // 0x100: not ours
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = b[q] < 0xffu ? nb[u[q]] : 0xffu;
+            int w = 0, nxt = 0;
+            if (out) {  // owner of the first position of the block in the chunk, then a forward walk
+                const int pf = max(lo, p0);
+                int l = 0, h = nv - 1;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (op[mid] <= pf) l = mid; else h = mid - 1;
                 }
-                vi[q] = f < total ? lo : -1;
-                w[q] = vi[q] >= 0 ? g.out_idx[op[lo] + (f - pre[lo])] : 0;
-            }
-            int b[UA], xw[UA];
-#pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                b[q] = vi[q] >= 0 ? g.lab[w[q]] : 0;
-                xw[q] = vi[q] >= 0 ? nb[w[q]] : -1;
+                w = l;
+                nxt = op[l + 1];
             }
 #pragma unroll
-            for (int q = 0; q < UA; ++q) {
-                if (vi[q] < 0) continue;
-                const int b2 = xw[q] >= 0 ? xw[q] : b[q];
-                const int a = a0[vi[q]], a2 = a1[vi[q]];
-                if (a != a2 || b[q] != b2) {
-                    atomicAdd(&dl[a * C + b[q]], -1);
-                    atomicAdd(&dl[a2 * C + b2], 1);
+            for (int q = 0; q < 8; ++q) {
+                if (b[q] == 0x100u) continue;
+                const unsigned bn = x[q] != 0xffu ? x[q] : b[q];
+                if (bn != b[q]) nlp[p0 + q] = (unsigned char)bn;
+                if (!out) continue;
+                while (p0 + q >= nxt) nxt = op[++w + 1];
+                const int va = a0[w], vb = a1[w];
+                const int ua = b[q] == 0xffu ? va : (int)b[q];  // a self-loop's far end is the vertex
+                const int ub = b[q] == 0xffu ? vb : (int)bn;
+                if (va != vb || ua != ub) {
+                    atomicAdd(&dl[va * C + ua], -1);
+                    atomicAdd(&dl[vb * C + ub], 1);
                 }
             }
         }
@@ -591,22 +815,13 @@ __global__ void __launch_bounds__(256) k_dense_delta(GDev g, const int *__restri
         if (dl[i]) atomicAdd(&delta[i], dl[i]);
 }
 
-// M += delta (delta cleared for the next batch); labels of accepted moves.
-__global__ void k_dense_apply(GDev g, DenseBM bm, int *__restrict__ delta, const int *__restrict__ nb) {
-    const int CC = g.C * g.C;
+// Labels of the accepted moves of one batch of several.
+__global__ void k_dense_apply(GDev g, const int *__restrict__ nb) {
     const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < CC + nbc; i += gridDim.x * blockDim.x) {
-        if (i < CC) {
-            const int x = delta[i];
-            if (x) {
-                bm.M[i] += x;
-                delta[i] = 0;
-            }
-        } else {
-            const int v = g.batch + (i - CC) * g.n_batches;
-            const int x = nb[v];
-            if (x >= 0) g.lab[v] = x;
-        }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbc; i += gridDim.x * blockDim.x) {
+        const int v = g.batch + i * g.n_batches;
+        const int x = nb[v];
+        if (x >= 0) g.lab[v] = x;
     }
 }
 
@@ -696,41 +911,110 @@ int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s) {
     const int CC = g.C * g.C;
     hipLaunchKernelGGL(k_zero, dim3(grid_for(CC, 256, 64)), dim3(256), 0, s, bm.M, CC);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(CC, 256, 64)), dim3(256), 0, s, delta, CC);
-    hipLaunchKernelGGL(k_ftab, dim3(FTAB_N / 256), dim3(256), 0, s, bm.ftab);
+    hipLaunchKernelGGL(k_ftab, dim3(grid_for((long long)bm.ftab_max + 1, 256, 8192)), dim3(256), 0, s, bm.ftab,
+                       bm.ftab_max);
     hipLaunchKernelGGL(k_dense_hist, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, s, g, bm.M);
-    hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(1024), 0, s, g, bm, (const long long *)nullptr,
+    hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, delta, (const long long *)nullptr,
                        (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr);
     SBP_LAUNCH_CHECK();
+    return dense_refresh_ends(g, bm, s);
+}
+
+int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s) {
+    if (g.n > 0) {
+        hipLaunchKernelGGL(k_dense_ends, dim3(grid_for((long long)g.n * 64, 256, 4096)), dim3(256), 0, s, g, bm);
+        SBP_LAUNCH_CHECK();
+    }
     return 0;
 }
 
 int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
-int g_delta_wgs = 1024;  // workgroups of the edge-parallel delta grid
+int g_delta_wgs = 1024; // workgroups of the update grid
+
+template <bool ENDS, bool TRACE, int CM>
+void launch_eval(int grid, hipStream_t s, const EvalArgs &a, const SweepTraceDev &tr) {
+    hipLaunchKernelGGL((k_dense_eval<ENDS, TRACE, CM>), dim3(grid), dim3(EVAL_T), 0, s, a, tr);
+}
+
+// Launches the evaluation for block capacity CM; returns its grid (the number
+// of statistics partials it writes).
+template <int CM>
+int run_eval(const GDev &g, const DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr, hipStream_t s) {
+    EvalArgs a{};
+    a.out_ptr = g.out_ptr;
+    a.in_ptr = g.in_ptr;
+    a.out_idx = g.out_idx;
+    a.in_idx = g.in_idx;
+    a.lab = g.lab;
+    a.M = bm.M;
+    a.dout = bm.dout;
+    a.din = bm.din;
+    a.fM = bm.fM;
+    a.ftab = bm.ftab;
+    a.nlo = bm.nl;
+    a.nli = bm.nl + bm.nl_in;
+    a.nb = ws.nb;
+    a.stats_part = ws.stats_part;
+    a.sum_part = ws.sum_part;
+    a.seed = g.seed;
+    a.beta = g.beta;
+    a.ftab_max = bm.ftab_max;
+    a.sweep = g.sweep;
+    a.n = g.n;
+    a.C = g.C;
+    a.batch = g.batch;
+    a.n_batches = g.n_batches;
+    a.eps = g.eps;
+    a.voff = g.voff;
+    const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
+    const int nchunks = (nbc + eval_chunk<CM>() - 1) / eval_chunk<CM>();
+    int grid = ws.nwg / 4 * eval_wgs_per_cu<CM>();  // every workgroup resident at once
+    if (g_eval_wgs > 0 && grid > g_eval_wgs) grid = g_eval_wgs;
+    if (grid > ws.nwg) grid = ws.nwg;
+    if (grid > nchunks) grid = nchunks;
+    if (grid < 1) grid = 1;
+    const bool ends = g.n_batches == 1;
+    const bool trace = tr.prop || tr.dS || tr.lnH || tr.margin || tr.accept || tr.status;
+    if (ends) {
+        if (trace) launch_eval<true, true, CM>(grid, s, a, tr);
+        else launch_eval<true, false, CM>(grid, s, a, tr);
+    } else {
+        if (trace) launch_eval<false, true, CM>(grid, s, a, tr);
+        else launch_eval<false, false, CM>(grid, s, a, tr);
+    }
+    return grid;
+}
 
 int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr,
                       sbp_sweep_stats_dev *stats, hipStream_t s) {
     const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
-    const int nchunks = (nbc + CH - 1) / CH;
-    int grid = nchunks < ws.nwg ? nchunks : ws.nwg;
-    if (g_eval_wgs > 0 && grid > g_eval_wgs) grid = g_eval_wgs;
-    if (grid < 1) grid = 1;
-    const size_t lds = (size_t)eval_offsets(g.C).bytes;
+    int grid;
     {
         ProfileScope prof("sweep_eval", s);
-        hipLaunchKernelGGL(k_dense_eval, dim3(grid), dim3(EVAL_T), lds, s, g, bm, ws.nb, tr, ws.stats_part,
-                           ws.sum_part);
+        if (g.C <= 16) grid = run_eval<16>(g, bm, ws, tr, s);
+        else if (g.C <= 32) grid = run_eval<32>(g, bm, ws, tr, s);
+        else if (g.C <= 48) grid = run_eval<48>(g, bm, ws, tr, s);
+        else grid = run_eval<64>(g, bm, ws, tr, s);
     }
     if (g.n_batches == 1) {
-        const size_t dl_lds = sizeof(int) * ((size_t)g.C * g.C + 4 * CH + 1);
-        int dgrid = (g.n + CH - 1) / CH;
-        if (dgrid > g_delta_wgs) dgrid = g_delta_wgs;
-        hipLaunchKernelGGL(k_dense_delta_edges, dim3(dgrid), dim3(EVAL_T), dl_lds, s, g, (const int *)ws.nb, ws.delta);
+        const size_t up_lds = sizeof(int) * ((size_t)g.C * g.C + 4 * CHU + 2);
+        int ugrid = (g.n + CHU - 1) / CHU;
+        if (ugrid > g_delta_wgs) ugrid = g_delta_wgs;
+        const bool vec = ((uintptr_t)g.out_idx % 16 == 0) && ((uintptr_t)g.in_idx % 16 == 0);
+        if (ugrid > 0) {
+            if (vec)
+                hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(EVAL_T), up_lds, s, g, bm,
+                                   (const unsigned char *)ws.nb, ws.delta);
+            else
+                hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(EVAL_T), up_lds, s, g, bm,
+                                   (const unsigned char *)ws.nb, ws.delta);
+        }
     } else {
         hipLaunchKernelGGL(k_dense_delta, dim3(grid), dim3(256), 0, s, g, (const int *)ws.nb, ws.delta);
+        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(nbc, 256, 2048)), dim3(256), 0, s, g, (const int *)ws.nb);
     }
-    hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(g.C * g.C + nbc, 256, 2048)), dim3(256), 0, s, g, bm, ws.delta,
-                       ws.nb);
-    hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(1024), 0, s, g, bm, ws.stats_part, ws.sum_part, grid, stats);
+    hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, ws.delta, ws.stats_part, ws.sum_part, grid,
+                       stats);
     SBP_LAUNCH_CHECK();
     return 0;
 }

@@ -141,7 +141,6 @@ enum { ACT_NONE = 0, ACT_SWEEP = 1, ACT_MERGE = 2, ACT_COMPACT = 3 };
 
 #define SBP_LEAF_MAX 256
 #define SBP_DENSE_MAX_C_DEV 64
-#define SBP_FTAB_N (1 << 18)  // entries of the f(x) = x ln x table
 
 // device image of the public sweep statistics record
 struct sbp_sweep_stats_dev {

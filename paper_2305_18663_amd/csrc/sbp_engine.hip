@@ -204,6 +204,7 @@ struct BMView {
 
 BMView bm_layout(void *base, int n, int e, int C) {
     (void)n;
+    const long long e_al = ((long long)(e > 0 ? e : 1) + 255) & ~255ll;
     Arena a(base, SIZE_MAX);
     if (!base) a = Arena::measure();
     BMView v{};
@@ -212,11 +213,15 @@ BMView bm_layout(void *base, int n, int e, int C) {
         v.d.C = C;
         v.d.M = a.take<int>((size_t)C * C);
         v.d.cdf = a.take<int>((size_t)C * C);
+        v.d.fM = a.take<double>((size_t)C * C);
         v.d.dout = a.take<int>(C);
         v.d.din = a.take<int>(C);
         v.d.dl = a.take<double>(1);
         v.delta = a.take<int>((size_t)C * C);
-        v.d.ftab = a.take<double>(SBP_FTAB_N);
+        v.d.ftab_max = (unsigned)(e > 0 ? e : 0);
+        v.d.ftab = a.take<double>((size_t)v.d.ftab_max + 1);
+        v.d.nl = a.take<unsigned char>(2 * (size_t)e_al);
+        v.d.nl_in = e_al;
         v.dl = v.d.dl;
         v.spare = a.take<long long>(1);
     } else {
@@ -968,8 +973,10 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
     sbp_sweep_stats_dev *st = stats ? (sbp_sweep_stats_dev *)stats : w.stats;
-    hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(1), 0, s, st);
-    SBP_LAUNCH_CHECK();
+    if (!bv.dense) {  // the dense tier's first batch starts the totals itself
+        hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(1), 0, s, st);
+        SBP_LAUNCH_CHECK();
+    }
     SweepTraceDev tr{};
     if (trace) {
         tr.prop = trace->prop;
@@ -996,6 +1003,7 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
             d.batch = b;
             if ((rc = dense_sweep_batch(d, bv.d, ds, tr, st, s))) return rc;
         }
+        if (d.n_batches > 1) return dense_refresh_ends(d, bv.d, s);
         return 0;
     }
     // sparse tier: hub list, then per batch: evaluate + apply, rebuild

@@ -148,14 +148,21 @@ struct DenseBM {
     int C;
     int *M;           // [C*C]
     int *cdf;         // [C*C] running sums of e_ts = M_ts + M_st over s
+    double *fM;       // [C*C] f(M_ab) = M_ab ln M_ab of the current M
     int *dout, *din;  // [C]
     double *dl;       // [1]
-    double *ftab;     // [SBP_FTAB_N] f(x) = x ln x for small integers
+    double *ftab;     // [ftab_max + 1] f(x) = x ln x for every count 0 <= x <= e
+    unsigned ftab_max;  // = max(e, 0): no entry of M and no block degree exceeds e
+    // Block of the far end of every edge end, one byte each, in CSR order:
+    // nl[0, e) for the out-ends, nl[nl_in, nl_in + e) for the in-ends;
+    // 0xff marks a self-loop (its far end is the vertex itself).
+    unsigned char *nl;
+    long long nl_in;
 };
 struct DenseScratch {
     int *delta;             // [C*C] change of M of one batch (kept zero between batches)
     int nwg;                // workgroups of the evaluation grid
-    int *nb;                // [n] accepted new label, else -1
+    int *nb;                // [n] accepted new label, else -1 (single batch: bytes, 0xff = stays)
     long long *stats_part;  // [nwg][4]
     double *sum_part;       // [nwg]
 };
@@ -163,6 +170,9 @@ int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s);
 int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr,
                       sbp_sweep_stats_dev *stats, hipStream_t s);
 int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *dS, double *dSl, hipStream_t s);
+// Recompute the per-end block bytes from the labels (after a sweep of several
+// batches, whose moves update M but not the bytes).
+int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s);
 int dense_workgroups();
 int dense_tune(const char *key, long long value);
 

@@ -45,7 +45,8 @@ def test_size_queries():
     L = sbp.lib()
     assert L.sbp_blockmodel_bytes(1000, 8000, 10) > 4 * 100
     dense = L.sbp_blockmodel_bytes(1000, 8000, 64)
-    assert dense >= 8 * (1 << 18)  # the dense tier carries the f(x) = x ln x table
+    # the dense tier carries f(x) = x ln x for every count up to e and a block byte per edge end
+    assert dense >= 8 * (8000 + 1) + 2 * 8000
     # the sparse tier stores rows, columns and proposal tables sized by the edges
     assert L.sbp_blockmodel_bytes(1000, 80000, 65) > L.sbp_blockmodel_bytes(1000, 8000, 65) + 8 * 72000
     assert L.sbp_blockmodel_bytes(0, 10, 1) == 0
