@@ -93,60 +93,21 @@ __device__ __forceinline__ double fx(const double *__restrict__ tab, unsigned n_
     return tab[min((unsigned)x, n_max)];
 }
 
-// M += delta (delta cleared), degrees, proposal tables and DL from M; sweep
-// totals.  One workgroup of four waves; a wave scans one row of proposal
-// table at a time (lane b <-> block b).
-constexpr int FIN_T = 256;
+// M += delta (delta cleared), f(M), block degrees and DL; sweep totals.  One
+// workgroup, a thread per entry of M: the statistics partials, M and the delta
+// are read together, degrees are exact LDS integer sums, and the DL sum is
+// taken in a fixed order.
+constexpr int FIN_T = 512;
 __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *__restrict__ delta,
                                                       const long long *__restrict__ stats_part,
                                                       const double *__restrict__ sum_part, int nwg,
                                                       sbp_sweep_stats_dev *__restrict__ stats) {
-    __shared__ int Ms[DC * DC];
     __shared__ int so[DC], si[DC];
     __shared__ double wred[FIN_T / 64], sred[FIN_T / 64];
     __shared__ long long lred[3][FIN_T / 64];
     const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double *tab = bm.ftab;
     const unsigned fmax = bm.ftab_max;
-    for (int i = tid; i < CC; i += FIN_T) {
-        const int d = delta[i];
-        int m = bm.M[i];
-        if (d) {
-            m += d;
-            bm.M[i] = m;
-            delta[i] = 0;
-        }
-        Ms[i] = m;
-    }
-    __syncthreads();
-    for (int t = wv; t < C; t += FIN_T / 64) {
-        const int mo = lane < C ? Ms[t * C + lane] : 0;  // M_tb
-        const int mi = lane < C ? Ms[lane * C + t] : 0;  // M_bt
-        int run = mo + mi;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(run, o, SBP_WAVE);
-            if (lane >= o) run += y;
-        }
-        if (lane < C) bm.cdf[t * C + lane] = run;
-        const long long dout = wave_sum_i64(mo), din = wave_sum_i64(mi);
-        if (lane == 0) {
-            so[t] = (int)dout;
-            si[t] = (int)din;
-            bm.dout[t] = (int)dout;
-            bm.din[t] = (int)din;
-        }
-    }
-    __syncthreads();
-    // L = sum f(M) - sum f(dout) - sum f(din), fixed order
-    double acc = 0.0;
-    for (int i = tid; i < CC; i += FIN_T) {
-        const double f = fx(tab, fmax, Ms[i]);
-        bm.fM[i] = f;
-        acc += f;
-    }
-    if (tid < C) acc -= fx(tab, fmax, so[tid]) + fx(tab, fmax, si[tid]);
-    acc = wave_sum(acc);
     long long a0 = 0, a1 = 0, a2 = 0;
     double sd = 0.0;
     if (stats)
@@ -156,6 +117,36 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
             a2 += stats_part[4 * w + 2];
             sd += sum_part[w];
         }
+    if (tid < C) {
+        so[tid] = 0;
+        si[tid] = 0;
+    }
+    __syncthreads();
+    // L = sum f(M) - sum f(dout) - sum f(din)
+    double acc = 0.0;
+    for (int i = tid; i < CC; i += FIN_T) {
+        const int d = delta[i];
+        int m = bm.M[i];
+        if (d) {
+            m += d;
+            bm.M[i] = m;
+            delta[i] = 0;
+        }
+        const double f = fx(tab, fmax, m);
+        bm.fM[i] = f;
+        acc += f;
+        const int row = i / C;
+        atomicAdd(&so[row], m);
+        atomicAdd(&si[i - row * C], m);
+    }
+    __syncthreads();
+    if (tid < C) {
+        const int o = so[tid], n = si[tid];
+        bm.dout[tid] = o;
+        bm.din[tid] = n;
+        acc -= fx(tab, fmax, o) + fx(tab, fmax, n);
+    }
+    acc = wave_sum(acc);
     a0 = wave_sum_i64(a0);
     a1 = wave_sum_i64(a1);
     a2 = wave_sum_i64(a2);
@@ -192,34 +183,38 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
     }
 }
 
-// Sum over the 16 lanes of a DPP row (a scoring group): four rotate-and-add
-// steps on the VALU, no LDS round trip.  Every lane of the row ends with the
-// sum; lanes may differ in rounding order, so one lane's value is used.
+// A DPP move of a double: both halves with the same control.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double row16_sum(double x) {
-    x += dpp_f64<0x128>(x);  // row_ror:8
-    x += dpp_f64<0x124>(x);  // row_ror:4
-    x += dpp_f64<0x122>(x);  // row_ror:2
-    x += dpp_f64<0x121>(x);  // row_ror:1
+// Sum over the 8 lanes of a scoring group (half a DPP row): pairs, quads, then
+// the mirrored half.  Each step adds the same two values on every lane, so the
+// whole group ends with one identical sum.
+__device__ __forceinline__ double grp8_sum(double x) {
+    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141>(x);  // row_half_mirror
     return x;
 }
 
-// Inclusive prefix sum over the 16 lanes of a DPP row.
-__device__ __forceinline__ int row16_scan(int x) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+// Inclusive prefix sum over the 8 lanes of a scoring group (gl = lane in the
+// group): row shifts, with the lanes whose source lies in the group before
+// left out.
+__device__ __forceinline__ int grp8_scan(int x, int gl) {
+    int y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    if (gl >= 1) x += y;
+    y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    if (gl >= 2) x += y;
+    y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    if (gl >= 4) x += y;
     return x;
 }
 
 constexpr int EVAL_T = 256;      // threads per workgroup
-constexpr int GS = 16;           // lanes per vertex in the scoring phase (one DPP row)
+constexpr int GS = 8;            // lanes per vertex in the scoring phase (half a DPP row)
 constexpr int NG = EVAL_T / GS;  // scoring groups per workgroup
 constexpr int SEG = 8;           // consecutive edge ends per thread in the histogram phase
 constexpr int LDS_CU = 160 * 1024;
@@ -247,7 +242,7 @@ struct EvalArgs {
 // rows are CM apart.
 template <int CM>
 struct EvalLds {
-    static constexpr int CH = CM >= 48 ? 32 : 48;  // vertices per chunk: four workgroups per CU up to 48 blocks
+    static constexpr int CH = CM >= 48 ? 32 : 64;  // vertices per chunk: four workgroups per CU up to 48 blocks
     static constexpr int RS = CM + 1;
     double fM[CM * RS];
     double fdo[CM], fdi[CM], inv[CM];
@@ -259,6 +254,7 @@ struct EvalLds {
     unsigned H[CH * CM];  // out-ends in the low 16 bits, in-ends in the high 16 bits
     int v[CH], r[CH], op[CH + 1], kout[CH], ip[CH + 1], kin[CH], pre[CH + 1], ell[CH], t0[CH], j0[CH];
     unsigned char items[NG][CM];
+    int ord[CH];  // scoring order: by degree, larger first
 };
 template <int CM>
 constexpr int eval_chunk() { return EvalLds<CM>::CH; }
@@ -276,14 +272,14 @@ constexpr int eval_wgs_per_cu() {
 //      its loads, then counts.  With ENDS the far-end blocks are the stored end
 //      bytes; otherwise (one batch of several) the ids are read and the labels
 //      gathered;
-//  (B) a group of GS lanes (one DPP row) scores one vertex per round: the
+//  (B) a group of GS lanes scores one vertex per round: the
 //      proposal from running sums of e_t0. built on the fly from M (exact
 //      integer row scans), the vertex's nonzero blocks t != r, s compacted into
 //      a list, then for every listed block the four changed entries of M --
 //      f of the old values from LDS, f of the new values gathered from the
-//      table, all gathers of the round (and of the 2x2 corner and the block
-//      degrees) in flight together -- the Hastings terms, row sums on DPP and
-//      the three logs of the wave's four vertices in one evaluation.
+//      table, a batch of gathers (with the 2x2 corner and the block degrees) in
+//      flight together -- the Hastings terms, group sums on DPP and
+//      the three logs of the wave's eight vertices in one evaluation.
 // The decision goes to nb: with ENDS one byte per vertex (0xff = stays),
 // otherwise an int (-1 = stays).  TRACE adds the per-vertex record.
 template <bool ENDS, bool TRACE, int CM>
@@ -292,6 +288,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
     constexpr int CH = Lds::CH;
     constexpr int RS = Lds::RS;
     constexpr int NQ = CM / GS;  // blocks per lane in the scoring phase
+    constexpr int BQ = NQ <= 4 ? NQ : 2;  // slots per batch of table gathers
     static_assert(CH % NG == 0, "every group scores the same number of vertices per chunk");
     __shared__ Lds L;
     const double *__restrict__ tab = a.ftab;
@@ -361,6 +358,14 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             }
             if (tid < CH) L.pre[tid + 1] = x;
             if (tid == 0) L.pre[0] = 0;
+            // scoring order: by degree, larger first, ties by position
+            const int key = tid < nv ? k : -1;
+            int rank = 0;
+            for (int j = 0; j < CH; ++j) {
+                const int kj = __builtin_amdgcn_readlane(key, j);
+                rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
+            }
+            if (tid < CH) L.ord[rank] = tid;
         }
         for (int i = tid; i < CH * CM; i += EVAL_T) L.H[i] = 0;
         __syncthreads();
@@ -474,10 +479,12 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             }
         }
         __syncthreads();
-        // (B) scoring, one vertex per group per round; every group runs the
-        // same number of rounds, so DPP and ballots see whole rows
+        // (B) scoring, one vertex per group per round, in degree order (so the
+        // eight vertices of a wave need about as many slots); every group runs
+        // the same number of rounds, so DPP and ballots see whole groups
         const unsigned below = (1u << gl) - 1u;
-        for (int vi = grp; vi < CH; vi += NG) {
+        for (int slot = grp; slot < CH; slot += NG) {
+            const int vi = L.ord[slot];
             const bool valid = vi < nv;
             int v = 0, r = 0, kout = 0, kin = 0, ell = 0, t0 = 0;
             uint64_t W1 = 0, W2 = 0, W3 = 0;
@@ -507,10 +514,10 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                 for (int q = 0; q < NQ; ++q) {
                     const int bb = q * GS + gl;
                     const int e = (!unif && bb < C) ? L.Ms[t0 * RS + bb] + L.Ms[bb * RS + t0] : 0;
-                    const int run = row16_scan(e);
+                    const int run = grp8_scan(e, gl);
                     const bool hit = !unif && bb < C && carry + run > x;
-                    const uint64_t m = (__ballot(hit) >> (wgrp * GS)) & ((1ull << GS) - 1);
-                    if (m && sp == C) sp = q * GS + __builtin_ctzll(m);
+                    const unsigned m = (unsigned)(__ballot(hit) >> (wgrp * GS)) & 0xffu;
+                    if (m && sp == C) sp = q * GS + __builtin_ctz(m);
                     carry += __shfl(run, wgrp * GS + GS - 1, SBP_WAVE);
                 }
                 s = unif ? (int)draw_idx(W2, (uint64_t)C) : sp;
@@ -524,7 +531,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             for (int q = 0; q < NQ; ++q) {
                 const int t = q * GS + gl;
                 const bool nz = act && t < C && t != r && t != s && Hv[t] != 0u;
-                const unsigned m = (unsigned)(__ballot(nz) >> (wgrp * GS)) & 0xffffu;
+                const unsigned m = (unsigned)(__ballot(nz) >> (wgrp * GS)) & 0xffu;
                 if (nz) items[n_it + __builtin_popcount(m & below)] = (unsigned char)t;
                 n_it += __builtin_popcount(m);
             }
@@ -538,51 +545,53 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             const bool is_m = gl < 4;
             const int cdeg = c == 0 ? L.dos[r] : c == 1 ? L.dos[s] : c == 2 ? L.dis[r] : L.dis[s];
             const int ddelta = c == 0 ? -kout : c == 1 ? kout : c == 2 ? -kin : kin;
-            const bool corner = act && gl < 8;
             const int c_new = is_m ? L.Ms[ca * RS + cb] + mdelta : cdeg + ddelta;
-            const double c_fnew = corner ? fx(tab, fmax, c_new) : 0.0;
-            // listed blocks: four changed entries each, up to NQ per lane, all
-            // table gathers issued before any use
+            const double c_fnew = act ? fx(tab, fmax, c_new) : 0.0;
             double dL = 0.0, qf = 0.0, qr = 0.0;
-            int ti[NQ];
-            unsigned hq[NQ];
+            // listed blocks: four changed entries each, BQ slots per batch with
+            // every table gather of the batch issued before any use
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int i = q * GS + gl;
-                ti[q] = i < n_it ? (int)items[i] : -1;
-                hq[q] = ti[q] >= 0 ? Hv[ti[q]] : 0u;
-            }
-            double fn[NQ][4];
+            for (int q0 = 0; q0 < NQ; q0 += BQ) {
+                int ti[BQ];
+                unsigned hq[BQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int t = ti[q] >= 0 ? ti[q] : 0;
-                const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
-                const int mrt = L.Ms[r * RS + t], mst = L.Ms[s * RS + t];
-                const int mtr = L.Ms[t * RS + r], mts = L.Ms[t * RS + s];
-                fn[q][0] = ko ? fx(tab, fmax, mrt - ko) : 0.0;
-                fn[q][1] = ko ? fx(tab, fmax, mst + ko) : 0.0;
-                fn[q][2] = ki ? fx(tab, fmax, mtr - ki) : 0.0;
-                fn[q][3] = ki ? fx(tab, fmax, mts + ki) : 0.0;
-                if (ti[q] >= 0) {  // Hastings terms while the gathers are in flight
-                    const double kt = (double)(ko + ki), iv = L.inv[t];
-                    qf += kt * (((double)(mts + mst) + eps) * iv);
-                    qr += kt * (((double)(mtr - ki + mrt - ko) + eps) * iv);
+                for (int q = 0; q < BQ; ++q) {
+                    const int i = (q0 + q) * GS + gl;
+                    ti[q] = i < n_it ? (int)items[i] : -1;
+                    hq[q] = ti[q] >= 0 ? Hv[ti[q]] : 0u;
+                }
+                double fn[BQ][4];
+#pragma unroll
+                for (int q = 0; q < BQ; ++q) {
+                    const int t = ti[q] >= 0 ? ti[q] : 0;
+                    const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
+                    const int mrt = L.Ms[r * RS + t], mst = L.Ms[s * RS + t];
+                    const int mtr = L.Ms[t * RS + r], mts = L.Ms[t * RS + s];
+                    fn[q][0] = ko ? fx(tab, fmax, mrt - ko) : 0.0;
+                    fn[q][1] = ko ? fx(tab, fmax, mst + ko) : 0.0;
+                    fn[q][2] = ki ? fx(tab, fmax, mtr - ki) : 0.0;
+                    fn[q][3] = ki ? fx(tab, fmax, mts + ki) : 0.0;
+                    if (ti[q] >= 0) {  // Hastings terms while the gathers are in flight
+                        const double kt = (double)(ko + ki), iv = L.inv[t];
+                        qf += kt * (((double)(mts + mst) + eps) * iv);
+                        qr += kt * (((double)(mtr - ki + mrt - ko) + eps) * iv);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < BQ; ++q) {
+                    if (ti[q] < 0) continue;
+                    const int t = ti[q];
+                    const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
+                    if (ko) dL += (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
+                    if (ki) dL += (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
                 }
             }
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (ti[q] < 0) continue;
-                const int t = ti[q];
-                const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
-                if (ko) dL += (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
-                if (ki) dL += (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
-            }
-            if (corner) {
+            if (act) {
                 const double c_fold = is_m ? L.fM[ca * RS + cb] : (c < 2 ? L.fdo[c == 0 ? r : s] : L.fdi[c == 2 ? r : s]);
                 dL += (is_m ? 1.0 : -1.0) * (c_fnew - c_fold);
             }
-            // Hastings terms of t = r and t = s (lanes 8-11): before, after
-            if (act && gl >= 8 && gl < 12) {
+            // Hastings terms of t = r and t = s (lanes 0-3): before, after
+            if (act && gl < 4) {
                 const int Mrr = L.Ms[r * RS + r], Mrs = L.Ms[r * RS + s], Msr = L.Ms[s * RS + r], Mss = L.Ms[s * RS + s];
                 const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s;
                 const int kk = c == 0 ? ko_r + ki_r + 2 * ell : c == 1 ? ko_s + ki_s : c == 2 ? ko_r + ki_r : ko_s + ki_s + 2 * ell;
@@ -593,9 +602,9 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                     if (c < 2) qf += term; else qr += term;
                 }
             }
-            dL = row16_sum(dL);
-            qf = row16_sum(qf);
-            qr = row16_sum(qr);
+            dL = grp8_sum(dL);
+            qf = grp8_sum(qf);
+            qr = grp8_sum(qr);
             // the three logs of the wave's 64/GS vertices in one evaluation
             double lg;
             {
@@ -611,7 +620,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             const double lnqr = __shfl(lg, 3 * wgrp + 0, SBP_WAVE);
             const double lnqf = __shfl(lg, 3 * wgrp + 1, SBP_WAVE);
             const double lnu = __shfl(lg, 3 * wgrp + 2, SBP_WAVE);
-            const double dS = -__shfl(dL, wgrp * GS, SBP_WAVE);
+            const double dS = -dL;
             const double lnH = (act && k > 0) ? lnqr - lnqf : 0.0;
             const double z = -a.beta * dS + lnH;
             const bool acc = act && lnu < z;
@@ -674,7 +683,8 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
 // workgroups need no ordering.  A thread takes SEG consecutive ends of the
 // chunk (its out-ends, then its in-ends) and issues all their loads and
 // decision gathers before any use.
-constexpr int CHU = 64;  // vertices per chunk of the update
+constexpr int CHU = 64;     // vertices per chunk of the update
+constexpr int UPD_T = 512;  // threads per update workgroup: a typical chunk in one pass
 // A thread takes an 8-aligned block of 8 consecutive end positions of the
 // chunk (its out-ends, then its in-ends): with VEC (16-byte aligned id
 // arrays) the ids come in two 16-byte loads, the end bytes in one 8-byte load
@@ -682,7 +692,7 @@ constexpr int CHU = 64;  // vertices per chunk of the update
 // outside the chunk are read but neither used nor written: their owners are
 // other workgroups.
 template <bool VEC>
-__global__ void __launch_bounds__(EVAL_T) k_dense_update(GDev g, DenseBM bm, const unsigned char *__restrict__ nb,
+__global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, const unsigned char *__restrict__ nb,
                                                         int *__restrict__ delta) {
     extern __shared__ __align__(16) char smem[];
     const int C = g.C, CC = C * C, tid = threadIdx.x;
@@ -693,7 +703,7 @@ __global__ void __launch_bounds__(EVAL_T) k_dense_update(GDev g, DenseBM bm, con
     int *a1 = a0 + CHU;      // [CHU] new label
     unsigned char *__restrict__ nlo = bm.nl;
     unsigned char *__restrict__ nli = bm.nl + bm.nl_in;
-    for (int i = tid; i < CC; i += EVAL_T) dl[i] = 0;
+    for (int i = tid; i < CC; i += UPD_T) dl[i] = 0;
     const int nchunks = (g.n + CHU - 1) / CHU;
     for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         __syncthreads();
@@ -714,7 +724,7 @@ __global__ void __launch_bounds__(EVAL_T) k_dense_update(GDev g, DenseBM bm, con
         const int o0 = op[0], o1 = op[nv], i0 = ip[0], i1 = ip[nv];
         const int bo0 = o0 >> 3, nbo = o1 > o0 ? ((o1 + 7) >> 3) - bo0 : 0;
         const int bi0 = i0 >> 3, nbi = i1 > i0 ? ((i1 + 7) >> 3) - bi0 : 0;
-        for (int rr = tid; rr < nbo + nbi; rr += EVAL_T) {
+        for (int rr = tid; rr < nbo + nbi; rr += UPD_T) {
             const bool out = rr < nbo;
             const int p0 = (out ? bo0 + rr : bi0 + (rr - nbo)) * 8;
             const int lo = out ? o0 : i0, hi = out ? o1 : i1;
@@ -767,7 +777,7 @@ __global__ void __launch_bounds__(EVAL_T) k_dense_update(GDev g, DenseBM bm, con
         }
     }
     __syncthreads();
-    for (int i = tid; i < CC; i += EVAL_T)
+    for (int i = tid; i < CC; i += UPD_T)
         if (dl[i]) atomicAdd(&delta[i], dl[i]);
 }
 
@@ -825,6 +835,18 @@ __global__ void k_dense_apply(GDev g, const int *__restrict__ nb) {
     }
 }
 
+// Running sum over b' <= lane of e_t,b' = M_t,b' + M_b',t (lane b <-> block b),
+// the table a block proposal draws from; every lane of the wave takes part.
+__device__ __forceinline__ long long running_e(const int *__restrict__ M, int C, int t, int lane) {
+    long long x = lane < C ? (long long)M[t * C + lane] + M[lane * C + t] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o, SBP_WAVE);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
 // Merge scoring on the dense tier, wave per block c, lane t <-> block t.
 __global__ void __launch_bounds__(256) k_dense_merge(GDev g, DenseBM bm, int *__restrict__ partner,
                                                     double *__restrict__ dS, double *__restrict__ dSl) {
@@ -844,14 +866,14 @@ __global__ void __launch_bounds__(256) k_dense_merge(GDev g, DenseBM bm, int *__
             cp = kk + (kk >= c);
         } else {
             const long long x0 = draw_idx(W.w[0], (uint64_t)dc);
-            const int t = __builtin_ctzll(__ballot(lane < C && (long long)bm.cdf[c * C + lane] > x0));
+            const int t = __builtin_ctzll(__ballot(lane < C && running_e(bm.M, C, c, lane) > x0));
             const long long dt = (long long)bm.dout[t] + bm.din[t];
             if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) {
                 const int kk = (int)draw_idx(W.w[2], (uint64_t)(C - 1));
                 cp = kk + (kk >= c);
             } else {
                 const long long x2 = draw_idx(W.w[2], (uint64_t)dt);
-                cp = __builtin_ctzll(__ballot(lane < C && (long long)bm.cdf[t * C + lane] > x2));
+                cp = __builtin_ctzll(__ballot(lane < C && running_e(bm.M, C, t, lane) > x2));
             }
         }
         if (cp == c) continue;
@@ -929,7 +951,7 @@ int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s) {
 }
 
 int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
-int g_delta_wgs = 1024; // workgroups of the update grid
+int g_delta_wgs = 512;  // workgroups of the update grid
 
 template <bool ENDS, bool TRACE, int CM>
 void launch_eval(int grid, hipStream_t s, const EvalArgs &a, const SweepTraceDev &tr) {
@@ -1003,10 +1025,10 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
         const bool vec = ((uintptr_t)g.out_idx % 16 == 0) && ((uintptr_t)g.in_idx % 16 == 0);
         if (ugrid > 0) {
             if (vec)
-                hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(EVAL_T), up_lds, s, g, bm,
+                hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(UPD_T), up_lds, s, g, bm,
                                    (const unsigned char *)ws.nb, ws.delta);
             else
-                hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(EVAL_T), up_lds, s, g, bm,
+                hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(UPD_T), up_lds, s, g, bm,
                                    (const unsigned char *)ws.nb, ws.delta);
         }
     } else {

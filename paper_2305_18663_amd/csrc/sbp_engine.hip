@@ -212,7 +212,6 @@ BMView bm_layout(void *base, int n, int e, int C) {
     if (v.dense) {
         v.d.C = C;
         v.d.M = a.take<int>((size_t)C * C);
-        v.d.cdf = a.take<int>((size_t)C * C);
         v.d.fM = a.take<double>((size_t)C * C);
         v.d.dout = a.take<int>(C);
         v.d.din = a.take<int>(C);

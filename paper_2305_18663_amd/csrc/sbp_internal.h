@@ -147,7 +147,6 @@ int dl_chunks_of(int e, int C);
 struct DenseBM {
     int C;
     int *M;           // [C*C]
-    int *cdf;         // [C*C] running sums of e_ts = M_ts + M_st over s
     double *fM;       // [C*C] f(M_ab) = M_ab ln M_ab of the current M
     int *dout, *din;  // [C]
     double *dl;       // [1]
