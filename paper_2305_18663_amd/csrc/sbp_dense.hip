@@ -79,6 +79,29 @@ __global__ void __launch_bounds__(256) k_dense_ends(GDev g, DenseBM bm) {
     }
 }
 
+// Vertex ranges of equal cost for a grid of G workgroups: cost(v) is the
+// number of edge ends of vertices below v plus wV per vertex below v, which is
+// monotone in v, so range w starts at the first v with cost(v) >= w/G of the
+// total.  out[0] = G, out[1 + w] for w = 0..G (out[1] = 0, out[1 + G] = n).
+__global__ void k_dense_bounds(GDev g, int G, int wV, int *__restrict__ out) {
+    if (G <= 0) {  // no ranges: the kernels deal chunks round robin
+        if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+        return;
+    }
+    const long long total = (long long)g.out_ptr[g.n] + g.in_ptr[g.n] + (long long)wV * g.n;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w <= G; w += gridDim.x * blockDim.x) {
+        const long long target = total * w / G;
+        int lo = 0, hi = g.n;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const long long c = (long long)g.out_ptr[mid] + g.in_ptr[mid] + (long long)wV * mid;
+            if (c >= target) hi = mid; else lo = mid + 1;
+        }
+        out[1 + w] = lo;
+        if (w == 0) out[0] = G;
+    }
+}
+
 // f(x) = x ln x for every count 0 <= x <= e (no entry of M and no block degree
 // can exceed the number of edges), computed on the device with the same xlogx
 // as a direct evaluation, so a lookup returns the very value a direct
@@ -318,9 +341,9 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
     const int nchunks = (nbc + CH - 1) / CH;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-        __syncthreads();  // previous chunk done with the LDS
         const int base = chunk * CH;
         const int nv = min(CH, nbc - base);
+        __syncthreads();  // previous chunk done with the LDS
         // (0) vertex data and words
         if (tid < 64) {
             int k = 0;
@@ -683,17 +706,22 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
 // workgroups need no ordering.  A thread takes SEG consecutive ends of the
 // chunk (its out-ends, then its in-ends) and issues all their loads and
 // decision gathers before any use.
-constexpr int CHU = 64;     // vertices per chunk of the update
-constexpr int UPD_T = 512;  // threads per update workgroup: a typical chunk in one pass
+constexpr int CHU = 256;     // vertices per chunk of the update
+constexpr int UPD_T = 1024;  // threads per update workgroup, one workgroup per CU
 // A thread takes an 8-aligned block of 8 consecutive end positions of the
 // chunk (its out-ends, then its in-ends): with VEC (16-byte aligned id
 // arrays) the ids come in two 16-byte loads, the end bytes in one 8-byte load
-// (the byte arrays are padded to 256), then the 8 decision gathers.  Bytes
-// outside the chunk are read but neither used nor written: their owners are
-// other workgroups.
+// (the byte arrays are padded to 256).  Bytes outside the chunk are read but
+// neither used nor written: their owners are other workgroups.  The decisions
+// of vertices [0, sl) are copied into LDS first (sl fills what the LDS of the
+// CU has left), so the far-end lookups of those vertices are LDS reads; the
+// rest are gathered.
 template <bool VEC>
 __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, const unsigned char *__restrict__ nb,
-                                                        int *__restrict__ delta) {
+                                                        int *__restrict__ delta, int sl) {
+    const int *ub = bm.bounds;
+    const bool ranged = ub[0] == (int)gridDim.x;
+    const int rb0 = ranged ? ub[1 + blockIdx.x] : 0, rb1 = ranged ? ub[2 + blockIdx.x] : 0;
     extern __shared__ __align__(16) char smem[];
     const int C = g.C, CC = C * C, tid = threadIdx.x;
     int *dl = (int *)smem;
@@ -701,13 +729,25 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
     int *ip = op + CHU + 1;  // [CHU + 1] first in-end
     int *a0 = ip + CHU + 1;  // [CHU] old label
     int *a1 = a0 + CHU;      // [CHU] new label
+    unsigned char *nbs = (unsigned char *)smem + ((sizeof(int) * (CC + 4 * CHU + 2) + 15) & ~(size_t)15);
     unsigned char *__restrict__ nlo = bm.nl;
     unsigned char *__restrict__ nli = bm.nl + bm.nl_in;
     for (int i = tid; i < CC; i += UPD_T) dl[i] = 0;
+    for (int i = tid; i < sl / 16; i += UPD_T) ((uint4 *)nbs)[i] = ((const uint4 *)nb)[i];
     const int nchunks = (g.n + CHU - 1) / CHU;
-    for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    for (int ci = 0;; ++ci) {
+        int base, nv;
+        if (ranged) {  // the workgroup's own range of vertices, in chunks
+            base = rb0 + ci * CHU;
+            if (base >= rb1) break;
+            nv = min(CHU, rb1 - base);
+        } else {
+            const int chunk = blockIdx.x + ci * gridDim.x;
+            if (chunk >= nchunks) break;
+            base = chunk * CHU;
+            nv = min(CHU, g.n - base);
+        }
         __syncthreads();
-        const int base = chunk * CHU, nv = min(CHU, g.n - base);
         if (tid <= nv) {
             const int v = base + tid;
             op[tid] = g.out_ptr[v];
@@ -747,7 +787,7 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
                 b[q] = in_run ? (((q < 4 ? bw.x : bw.y) >> (8 * (q & 3))) & 0xffu) : 0x100u;  // 0x100: not ours
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = b[q] < 0xffu ? nb[u[q]] : 0xffu;
+            for (int q = 0; q < 8; ++q) x[q] = b[q] < 0xffu ? (u[q] < sl ? (unsigned)nbs[u[q]] : (unsigned)nb[u[q]]) : 0xffu;
             int w = 0, nxt = 0;
             if (out) {  // owner of the first position of the block in the chunk, then a forward walk
                 const int pf = max(lo, p0);
@@ -916,6 +956,25 @@ int g_dense_wgs = 0;
 
 }  // namespace
 
+// LDS one workgroup may use (the device's limit, queried once; opting the
+// update kernel in to more than 64 KB of dynamic LDS).
+int g_lds_block = 0;
+int dense_lds_per_block() {
+    if (g_lds_block == 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) {
+            if (v > LDS_CU) v = LDS_CU;
+        } else {
+            v = 65536;
+        }
+        (void)hipFuncSetAttribute((const void *)k_dense_update<true>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipFuncSetAttribute((const void *)k_dense_update<false>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        g_lds_block = v;
+    }
+    return g_lds_block;
+}
+
 int dense_workgroups() {
     if (g_dense_wgs == 0) {
         int dev = 0, cus = 256;
@@ -929,6 +988,31 @@ int dense_workgroups() {
     return g_dense_wgs;
 }
 
+int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
+int g_delta_wgs = 512;  // workgroups of the update grid
+
+// Grid of the evaluation for C blocks and nbc batch vertices (every
+// workgroup resident at once), and of the single-batch update.
+int eval_grid(int C, int nbc, int nwg) {
+    const int per_cu = C <= 16 ? eval_wgs_per_cu<16>() : C <= 32 ? eval_wgs_per_cu<32>()
+                     : C <= 48 ? eval_wgs_per_cu<48>() : eval_wgs_per_cu<64>();
+    const int ch = C <= 16 ? eval_chunk<16>() : C <= 32 ? eval_chunk<32>() : C <= 48 ? eval_chunk<48>() : eval_chunk<64>();
+    const int nchunks = (nbc + ch - 1) / ch;
+    int grid = nwg / 4 * per_cu;
+    if (g_eval_wgs > 0 && grid > g_eval_wgs) grid = g_eval_wgs;
+    if (grid > nwg) grid = nwg;
+    if (grid > nchunks) grid = nchunks;
+    return grid < 1 ? 1 : grid;
+}
+int update_grid(int n, int nwg) {
+    const int cus = nwg / 4 > 0 ? nwg / 4 : 1;
+    int ugrid = (n + CHU - 1) / CHU;
+    if (ugrid > g_delta_wgs) ugrid = g_delta_wgs;
+    if (ugrid > cus) ugrid = cus;
+    return ugrid;
+}
+constexpr int UPDATE_VERTEX_COST = 2;  // a vertex's head work, in edge ends
+
 int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s) {
     const int CC = g.C * g.C;
     hipLaunchKernelGGL(k_zero, dim3(grid_for(CC, 256, 64)), dim3(256), 0, s, bm.M, CC);
@@ -938,6 +1022,10 @@ int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_hist, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, s, g, bm.M);
     hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, delta, (const long long *)nullptr,
                        (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr);
+    // balanced vertex ranges for the single-batch update grid
+    const int gu = update_grid(g.n, dense_workgroups());
+    hipLaunchKernelGGL(k_dense_bounds, dim3(grid_for(gu + 1, 256, 16)), dim3(256), 0, s, g,
+                       gu <= SBP_DENSE_BOUNDS - 2 ? gu : 0, UPDATE_VERTEX_COST, bm.bounds);
     SBP_LAUNCH_CHECK();
     return dense_refresh_ends(g, bm, s);
 }
@@ -949,9 +1037,6 @@ int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s) {
     }
     return 0;
 }
-
-int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
-int g_delta_wgs = 512;  // workgroups of the update grid
 
 template <bool ENDS, bool TRACE, int CM>
 void launch_eval(int grid, hipStream_t s, const EvalArgs &a, const SweepTraceDev &tr) {
@@ -989,12 +1074,7 @@ int run_eval(const GDev &g, const DenseBM &bm, DenseScratch &ws, const SweepTrac
     a.eps = g.eps;
     a.voff = g.voff;
     const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
-    const int nchunks = (nbc + eval_chunk<CM>() - 1) / eval_chunk<CM>();
-    int grid = ws.nwg / 4 * eval_wgs_per_cu<CM>();  // every workgroup resident at once
-    if (g_eval_wgs > 0 && grid > g_eval_wgs) grid = g_eval_wgs;
-    if (grid > ws.nwg) grid = ws.nwg;
-    if (grid > nchunks) grid = nchunks;
-    if (grid < 1) grid = 1;
+    const int grid = eval_grid(g.C, nbc, ws.nwg);
     const bool ends = g.n_batches == 1;
     const bool trace = tr.prop || tr.dS || tr.lnH || tr.margin || tr.accept || tr.status;
     if (ends) {
@@ -1019,17 +1099,22 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
         else grid = run_eval<64>(g, bm, ws, tr, s);
     }
     if (g.n_batches == 1) {
-        const size_t up_lds = sizeof(int) * ((size_t)g.C * g.C + 4 * CHU + 2);
-        int ugrid = (g.n + CHU - 1) / CHU;
-        if (ugrid > g_delta_wgs) ugrid = g_delta_wgs;
+        // one workgroup per CU; the decisions of the first sl vertices in the
+        // LDS the workgroup leaves free
+        const int ugrid = update_grid(g.n, ws.nwg);
+        const size_t fixed = (sizeof(int) * ((size_t)g.C * g.C + 4 * CHU + 2) + 15) & ~(size_t)15;
+        const size_t budget = (size_t)dense_lds_per_block() - 1024;
+        size_t sl = budget > fixed ? budget - fixed : 0;
+        if (sl > (size_t)g.n) sl = (size_t)g.n;
+        sl &= ~(size_t)15;
         const bool vec = ((uintptr_t)g.out_idx % 16 == 0) && ((uintptr_t)g.in_idx % 16 == 0);
         if (ugrid > 0) {
             if (vec)
-                hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(UPD_T), up_lds, s, g, bm,
-                                   (const unsigned char *)ws.nb, ws.delta);
+                hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(UPD_T), fixed + sl, s, g, bm,
+                                   (const unsigned char *)ws.nb, ws.delta, (int)sl);
             else
-                hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(UPD_T), up_lds, s, g, bm,
-                                   (const unsigned char *)ws.nb, ws.delta);
+                hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(UPD_T), fixed + sl, s, g, bm,
+                                   (const unsigned char *)ws.nb, ws.delta, (int)sl);
         }
     } else {
         hipLaunchKernelGGL(k_dense_delta, dim3(grid), dim3(256), 0, s, g, (const int *)ws.nb, ws.delta);

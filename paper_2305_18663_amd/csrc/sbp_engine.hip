@@ -221,6 +221,7 @@ BMView bm_layout(void *base, int n, int e, int C) {
         v.d.ftab = a.take<double>((size_t)v.d.ftab_max + 1);
         v.d.nl = a.take<unsigned char>(2 * (size_t)e_al);
         v.d.nl_in = e_al;
+        v.d.bounds = a.take<int>(SBP_DENSE_BOUNDS);
         v.dl = v.d.dl;
         v.spare = a.take<long long>(1);
     } else {

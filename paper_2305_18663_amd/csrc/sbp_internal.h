@@ -157,7 +157,11 @@ struct DenseBM {
     // 0xff marks a self-loop (its far end is the vertex itself).
     unsigned char *nl;
     long long nl_in;
+    // Vertex ranges of the single-batch update: [0] = the grid they were made
+    // for (0: none), [1 + w] = first vertex of workgroup w, [1 + grid] = n.
+    int *bounds;
 };
+#define SBP_DENSE_BOUNDS 1026
 struct DenseScratch {
     int *delta;             // [C*C] change of M of one batch (kept zero between batches)
     int nwg;                // workgroups of the evaluation grid
