@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
     constexpr int CH = Lds::CH;
     constexpr int RS = Lds::RS;
     constexpr int NQ = CM / GS;  // blocks per lane in the scoring phase
-    constexpr int BQ = NQ <= 4 ? NQ : 2;  // slots per batch of table gathers
+    constexpr int BQ = NQ < 2 ? NQ : 2;  // slots per batch of table gathers
     static_assert(CH % NG == 0, "every group scores the same number of vertices per chunk");
     __shared__ Lds L;
     const double *__restrict__ tab = a.ftab;
@@ -569,44 +569,47 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             const int cdeg = c == 0 ? L.dos[r] : c == 1 ? L.dos[s] : c == 2 ? L.dis[r] : L.dis[s];
             const int ddelta = c == 0 ? -kout : c == 1 ? kout : c == 2 ? -kin : kin;
             const int c_new = is_m ? L.Ms[ca * RS + cb] + mdelta : cdeg + ddelta;
-            const double c_fnew = act ? fx(tab, fmax, c_new) : 0.0;
+            const double c_fnew = fx(tab, fmax, act ? c_new : 0);
             double dL = 0.0, qf = 0.0, qr = 0.0;
-            // listed blocks: four changed entries each, BQ slots per batch with
-            // every table gather of the batch issued before any use
+            // listed blocks: four changed entries each, BQ slots per batch, a
+            // batch only when a group of the wave needs it.  Within a batch no
+            // branches: a slot without a block, or a count of zero, loads f(0)
+            // (one line for the whole wave) and contributes an exact zero.
 #pragma unroll
             for (int q0 = 0; q0 < NQ; q0 += BQ) {
+                if (!__any(q0 * GS < n_it)) break;
                 int ti[BQ];
                 unsigned hq[BQ];
 #pragma unroll
                 for (int q = 0; q < BQ; ++q) {
                     const int i = (q0 + q) * GS + gl;
-                    ti[q] = i < n_it ? (int)items[i] : -1;
-                    hq[q] = ti[q] >= 0 ? Hv[ti[q]] : 0u;
+                    const int t = items[i];
+                    ti[q] = i < n_it ? t : 0;
+                    hq[q] = i < n_it ? Hv[ti[q]] : 0u;
                 }
                 double fn[BQ][4];
 #pragma unroll
                 for (int q = 0; q < BQ; ++q) {
-                    const int t = ti[q] >= 0 ? ti[q] : 0;
+                    const int t = ti[q];
                     const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
                     const int mrt = L.Ms[r * RS + t], mst = L.Ms[s * RS + t];
                     const int mtr = L.Ms[t * RS + r], mts = L.Ms[t * RS + s];
-                    fn[q][0] = ko ? fx(tab, fmax, mrt - ko) : 0.0;
-                    fn[q][1] = ko ? fx(tab, fmax, mst + ko) : 0.0;
-                    fn[q][2] = ki ? fx(tab, fmax, mtr - ki) : 0.0;
-                    fn[q][3] = ki ? fx(tab, fmax, mts + ki) : 0.0;
-                    if (ti[q] >= 0) {  // Hastings terms while the gathers are in flight
-                        const double kt = (double)(ko + ki), iv = L.inv[t];
-                        qf += kt * (((double)(mts + mst) + eps) * iv);
-                        qr += kt * (((double)(mtr - ki + mrt - ko) + eps) * iv);
-                    }
+                    fn[q][0] = fx(tab, fmax, ko ? mrt - ko : 0);
+                    fn[q][1] = fx(tab, fmax, ko ? mst + ko : 0);
+                    fn[q][2] = fx(tab, fmax, ki ? mtr - ki : 0);
+                    fn[q][3] = fx(tab, fmax, ki ? mts + ki : 0);
+                    // Hastings terms while the gathers are in flight (zero for an empty slot)
+                    const double kt = (double)(ko + ki), iv = L.inv[t];
+                    qf += kt * (((double)(mts + mst) + eps) * iv);
+                    qr += kt * (((double)(mtr - ki + mrt - ko) + eps) * iv);
                 }
 #pragma unroll
                 for (int q = 0; q < BQ; ++q) {
-                    if (ti[q] < 0) continue;
                     const int t = ti[q];
                     const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
-                    if (ko) dL += (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
-                    if (ki) dL += (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
+                    const double d_out = (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
+                    const double d_in = (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
+                    dL += (ko ? d_out : 0.0) + (ki ? d_in : 0.0);
                 }
             }
             if (act) {
