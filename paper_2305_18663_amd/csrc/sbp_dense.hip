@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                 kout = L.kout[vi];
                 kin = L.kin[vi];
                 ell = L.ell[vi];
-                t0 = L.t0[vi];
+                t0 = kout + kin > 0 ? L.t0[vi] : 0;
                 W1 = L.W[0][vi];
                 W2 = L.W[1][vi];
                 W3 = L.W[2][vi];
@@ -536,11 +536,12 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     const int bb = q * GS + gl;
-                    const int e = (!unif && bb < C) ? L.Ms[t0 * RS + bb] + L.Ms[bb * RS + t0] : 0;
+                    const int e0 = L.Ms[t0 * RS + bb] + L.Ms[bb * RS + t0];  // within the padded rows
+                    const int e = (!unif && bb < C) ? e0 : 0;
                     const int run = grp8_scan(e, gl);
                     const bool hit = !unif && bb < C && carry + run > x;
                     const unsigned m = (unsigned)(__ballot(hit) >> (wgrp * GS)) & 0xffu;
-                    if (m && sp == C) sp = q * GS + __builtin_ctz(m);
+                    sp = (m && sp == C) ? q * GS + __builtin_ctz(m) : sp;
                     carry += __shfl(run, wgrp * GS + GS - 1, SBP_WAVE);
                 }
                 s = unif ? (int)draw_idx(W2, (uint64_t)C) : sp;
@@ -553,7 +554,8 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int t = q * GS + gl;
-                const bool nz = act && t < C && t != r && t != s && Hv[t] != 0u;
+                const unsigned hv = Hv[t];  // within the padded row
+                const bool nz = act && t < C && t != r && t != s && hv != 0u;
                 const unsigned m = (unsigned)(__ballot(nz) >> (wgrp * GS)) & 0xffu;
                 if (nz) items[n_it + __builtin_popcount(m & below)] = (unsigned char)t;
                 n_it += __builtin_popcount(m);
@@ -616,17 +618,18 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                 const double c_fold = is_m ? L.fM[ca * RS + cb] : (c < 2 ? L.fdo[c == 0 ? r : s] : L.fdi[c == 2 ? r : s]);
                 dL += (is_m ? 1.0 : -1.0) * (c_fnew - c_fold);
             }
-            // Hastings terms of t = r and t = s (lanes 0-3): before, after
-            if (act && gl < 4) {
+            // Hastings terms of t = r and t = s (lanes 0-3): before, after;
+            // every lane evaluates, lanes 4-7 and idle vertices add zero
+            {
                 const int Mrr = L.Ms[r * RS + r], Mrs = L.Ms[r * RS + s], Msr = L.Ms[s * RS + r], Mss = L.Ms[s * RS + s];
                 const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s;
                 const int kk = c == 0 ? ko_r + ki_r + 2 * ell : c == 1 ? ko_s + ki_s : c == 2 ? ko_r + ki_r : ko_s + ki_s + 2 * ell;
                 const int num = c == 0 ? Mrs + Msr : c == 1 ? 2 * Mss : c == 2 ? 2 * (Mrr + drr) : Msr + dsr + Mrs + drs;
                 const int den = c == 0 ? L.dsum[r] : c == 1 ? L.dsum[s] : c == 2 ? L.dsum[r] - k : L.dsum[s] + k;
-                if (kk) {
-                    const double term = (double)kk * (((double)num + eps) / ((double)den + epsC));
-                    if (c < 2) qf += term; else qr += term;
-                }
+                const double term = (double)kk * (((double)num + eps) / ((double)den + epsC));
+                const bool use = act && gl < 4 && kk != 0;
+                qf += use && c < 2 ? term : 0.0;
+                qr += use && c >= 2 ? term : 0.0;
             }
             dL = grp8_sum(dL);
             qf = grp8_sum(qf);
