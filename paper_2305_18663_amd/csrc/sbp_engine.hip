@@ -120,15 +120,19 @@ __global__ void k_hub_list(const int *__restrict__ optr, const int *__restrict__
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         if ((optr[v + 1] - optr[v]) + (iptr[v + 1] - iptr[v]) > SBP_LEAF_MAX) hub[atomicAdd(count, 1)] = v;
 }
-// sweep totals from the per-vertex status (one workgroup, fixed order)
-__global__ void __launch_bounds__(1024) k_sweep_stats(const signed char *__restrict__ status, const double *__restrict__ dS,
-                                                      int n, int batch, int n_batches, const double *__restrict__ dl,
-                                                      sbp_sweep_stats_dev *__restrict__ st) {
-    __shared__ long long a[16], b[16], c[16];
-    __shared__ double d[16];
+// sweep totals from the per-vertex status: per-workgroup partials over a fixed
+// split of the batch's vertices, then one workgroup adds them in order
+__global__ void __launch_bounds__(256) k_sweep_stats_part(const signed char *__restrict__ status,
+                                                         const double *__restrict__ dS, int n, int batch,
+                                                         int n_batches, long long *__restrict__ part,
+                                                         double *__restrict__ sum_part) {
+    __shared__ long long a[4], b[4], c[4];
+    __shared__ double d[4];
     long long np = 0, ns = 0, na = 0;
     double sd = 0.0;
-    for (int v = batch + n_batches * (int)threadIdx.x; v < n; v += n_batches * 1024) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x;; i += (long long)gridDim.x * 256) {
+        const long long v = batch + n_batches * i;
+        if (v >= n) break;
         ++np;
         const int x = status[v];
         if (x < 0) ++ns;
@@ -149,14 +153,37 @@ __global__ void __launch_bounds__(1024) k_sweep_stats(const signed char *__restr
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 0; w < 16; ++w) {
-            st->proposals += a[w];
-            st->self_proposals += b[w];
-            st->accepted += c[w];
-            st->sum_dS_accepted += d[w];
+        long long p = 0, q = 0, r = 0;
+        double t = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            p += a[w];
+            q += b[w];
+            r += c[w];
+            t += d[w];
         }
-        if (dl) st->dl_after = *dl;
+        part[4 * blockIdx.x + 0] = p;
+        part[4 * blockIdx.x + 1] = q;
+        part[4 * blockIdx.x + 2] = r;
+        part[4 * blockIdx.x + 3] = 0;
+        sum_part[blockIdx.x] = t;
     }
+}
+__global__ void k_sweep_stats_final(const long long *__restrict__ part, const double *__restrict__ sum_part, int nblk,
+                                    const double *__restrict__ dl, sbp_sweep_stats_dev *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    long long p = 0, q = 0, r = 0;
+    double t = 0.0;
+    for (int w = 0; w < nblk; ++w) {
+        p += part[4 * w + 0];
+        q += part[4 * w + 1];
+        r += part[4 * w + 2];
+        t += sum_part[w];
+    }
+    st->proposals += p;
+    st->self_proposals += q;
+    st->accepted += r;
+    st->sum_dS_accepted += t;
+    if (dl) st->dl_after = *dl;
 }
 __global__ void k_copy_dl(const double *__restrict__ src, double *__restrict__ dst) { *dst = *src; }
 __global__ void k_relabel_map(int *__restrict__ lab, const int *__restrict__ map, int n) {
@@ -1029,8 +1056,11 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         GDev d2 = d;
         d2.action = ACT_NONE;
         if ((rc = build_one(d2, w.u, bv, s))) return rc;
-        hipLaunchKernelGGL(k_sweep_stats, dim3(1), dim3(1024), 0, s, (const signed char *)w.status, (const double *)tr.dS,
-                           g->n, b, d.n_batches, (const double *)bv.dl, st);
+        const int nblk = std::max(1, std::min(dense_workgroups(), (int)((g->n / d.n_batches + 255) / 256)));
+        hipLaunchKernelGGL(k_sweep_stats_part, dim3(nblk), dim3(256), 0, s, (const signed char *)w.status,
+                           (const double *)tr.dS, g->n, b, d.n_batches, w.stats_part, w.sum_part);
+        hipLaunchKernelGGL(k_sweep_stats_final, dim3(1), dim3(64), 0, s, (const long long *)w.stats_part,
+                           (const double *)w.sum_part, nblk, (const double *)bv.dl, st);
         SBP_LAUNCH_CHECK();
     }
     return 0;

@@ -463,18 +463,204 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
 }
 
 // Workgroup per hub (more than 256 edge ends): keys sorted in global scratch.
-constexpr int HUB_THREADS = 1024;
+constexpr int HUB_THREADS = 512;
 constexpr size_t HUB_SLOT_INTS = 4 * (size_t)SBP_MAX_DEGREE_DEV;
+constexpr int HUB_LDS = 8192;  // hubs with at most this many sort keys work in LDS
+
+// The move terms of a hub from its distinct neighbour blocks (dt, packed
+// counts dk = out | in << 16), every thread of the workgroup taking items;
+// partial sums are reduced per wave and then in wave order, so the result
+// does not depend on timing.
+__device__ __forceinline__ MoveOut move_terms_block(const GDev &d, const SparseBM &bm, int r, int s, const int *dt,
+                                                    const int *dk, int D, int ell, int kout, int kin, double lnu,
+                                                    double *red_d, int *red_i) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double eps = (double)d.eps;
+    const double epsC = (double)d.eps * (double)d.C;
+    double dL = 0.0, qf = 0.0, qr = 0.0;
+    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
+    for (int i = tid; i < D; i += HUB_THREADS) {
+        const int t = dt[i], ko = dk[i] & 0xffff, ki = dk[i] >> 16;
+        if (t == r) {
+            ko_r = ko;
+            ki_r = ki;
+            continue;
+        }
+        if (t == s) {
+            ko_s = ko;
+            ki_s = ki;
+            continue;
+        }
+        const int Mrt = m_get(bm, r, t), Mst = m_get(bm, s, t);
+        const int Mtr = m_get(bm, t, r), Mts = m_get(bm, t, s);
+        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
+        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
+        const double kt = (double)(ko + ki);
+        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
+        qf += kt * (((double)(Mts + Mst) + eps) / den);
+        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+    }
+    dL = wave_sum(dL);
+    qf = wave_sum(qf);
+    qr = wave_sum(qr);
+    ko_r = wave_sum_i32(ko_r);
+    ki_r = wave_sum_i32(ki_r);
+    ko_s = wave_sum_i32(ko_s);
+    ki_s = wave_sum_i32(ki_s);
+    if (lane == 0) {
+        red_d[3 * wv + 0] = dL;
+        red_d[3 * wv + 1] = qf;
+        red_d[3 * wv + 2] = qr;
+        red_i[4 * wv + 0] = ko_r;
+        red_i[4 * wv + 1] = ki_r;
+        red_i[4 * wv + 2] = ko_s;
+        red_i[4 * wv + 3] = ki_s;
+    }
+    __syncthreads();
+    MoveOut o;
+    o.s = s;
+    if (tid == 0) {
+        dL = qf = qr = 0.0;
+        ko_r = ki_r = ko_s = ki_s = 0;
+        for (int w = 0; w < HUB_THREADS / 64; ++w) {
+            dL += red_d[3 * w + 0];
+            qf += red_d[3 * w + 1];
+            qr += red_d[3 * w + 2];
+            ko_r += red_i[4 * w + 0];
+            ki_r += red_i[4 * w + 1];
+            ko_s += red_i[4 * w + 2];
+            ki_s += red_i[4 * w + 3];
+        }
+        const int Mrr = m_get(bm, r, r), Mrs = m_get(bm, r, s), Msr = m_get(bm, s, r), Mss = m_get(bm, s, s);
+        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
+        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
+        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
+        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
+        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
+        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
+        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
+        const double k = (double)(kout + kin);
+        const double d_r = dor + dir, d_s = dos + dis;
+        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
+        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
+        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
+        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
+        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
+        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
+        o.dS = -dL;
+        o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
+        const double z = -d.beta * o.dS + o.lnH;
+        o.margin = z - lnu;
+        o.accept = lnu < z;
+    }
+    return o;
+}
+
+// One hub: its sort keys (2 * neighbour block + in-end flag, self-loop ends
+// padded out) sorted by a bitonic network in K, the runs of equal block by
+// wave 0 into (Dt, Dk), then the move terms.  K, Dt, Dk hold m, kk, kk ints;
+// with the LDS arrays the whole hub stays on the CU.
+__device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int v, int r, int s, int op, int kout,
+                                         int ip, int kin, int m, double lnu, int *K, int *Dt, int *Dk, int *nb,
+                                         const SweepTraceDev &tr, int *red, int *s_ell, int *s_D, double *red_d,
+                                         int *red_i) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int k = kout + kin;
+    int ell = 0;
+    for (int j = tid; j < m; j += HUB_THREADS) {
+        int key = KEY_PAD;
+        if (j < k) {
+            const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
+            if (u == v) {
+                if (j < kout) ++ell;
+            } else {
+                key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
+            }
+        }
+        K[j] = key;
+    }
+    ell = wave_sum_i32(ell);
+    if (lane == 0) red[wv] = ell;
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int w = 0; w < HUB_THREADS / 64; ++w) t += red[w];
+        *s_ell = t;
+    }
+    for (int size = 2; size <= m; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = tid; q < (m >> 1); q += HUB_THREADS) {
+                const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
+                const bool asc = (i & size) == 0;
+                const int a = K[i], b = K[j];
+                if ((a > b) == asc) {
+                    K[i] = b;
+                    K[j] = a;
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+    ell = *s_ell;
+    const int kk = k - 2 * ell;
+    // run starts, in order, by wave 0 scanning 64 positions at a time
+    if (wv == 0) {
+        int D = 0;
+        int pend_idx = -1, pend_p = 0, pend_key = 0, evens = 0, pend_evens = 0;
+        for (int base = 0; base < kk; base += 64) {
+            const int p = base + lane;
+            const int key = p < kk ? K[p] : KEY_PAD;
+            const int prev = (p > 0 && p < kk) ? K[p - 1] : -2;
+            const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
+            const bool ev = p < kk && !(key & 1);
+            const uint64_t sm = __ballot(st), em = __ballot(ev);
+            // close runs: every start in this chunk ends the previous run
+            uint64_t rest = sm;
+            while (rest) {
+                const int b = __builtin_ctzll(rest);
+                rest &= rest - 1;
+                const int pos = base + b;
+                const int ev_before = evens + __popcll(em & ((b ? (~0ull >> (64 - b)) : 0ull)));
+                if (pend_idx >= 0 && lane == 0) {
+                    const int ko = ev_before - pend_evens;
+                    Dt[pend_idx] = pend_key >> 1;
+                    Dk[pend_idx] = ko | (((pos - pend_p) - ko) << 16);
+                }
+                pend_idx = D++;
+                pend_p = pos;
+                pend_key = __shfl(key, b, SBP_WAVE);
+                pend_evens = ev_before;
+            }
+            evens += __popcll(em);
+        }
+        if (pend_idx >= 0 && lane == 0) {
+            const int ko = evens - pend_evens;
+            Dt[pend_idx] = pend_key >> 1;
+            Dk[pend_idx] = ko | (((kk - pend_p) - ko) << 16);
+        }
+        if (lane == 0) *s_D = D;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const MoveOut o = move_terms_block(d, bm, r, s, Dt, Dk, *s_D, ell, kout, kin, lnu, red_d, red_i);
+    if (tid == 0) record_move(d, v, r, o, false, nb, tr);
+}
+
+// Sweep evaluation of hub vertices (more than SBP_LEAF_MAX edge ends): a
+// workgroup per hub.
 __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restrict__ G, const int *__restrict__ starts,
                                                            int nG, int n_items, SparseBM bm, int *__restrict__ nb,
                                                            SweepTraceDev tr, int *__restrict__ scratch) {
-    __shared__ int red[HUB_THREADS / 64];
+    __shared__ int Ks[HUB_LDS], Dts[HUB_LDS], Dks[HUB_LDS];
+    __shared__ int red[HUB_THREADS / 64], red_i[4 * (HUB_THREADS / 64)];
+    __shared__ double red_d[3 * (HUB_THREADS / 64)];
     __shared__ int s_ell, s_D;
     int *Kg = scratch + (size_t)blockIdx.x * HUB_SLOT_INTS;
-    int *Dt = Kg + SBP_MAX_DEGREE_DEV;
-    int *Dko = Dt + SBP_MAX_DEGREE_DEV;
-    int *Dki = Dko + SBP_MAX_DEGREE_DEV;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int *Dtg = Kg + SBP_MAX_DEGREE_DEV;
+    int *Dkg = Dtg + SBP_MAX_DEGREE_DEV;
+    const int tid = threadIdx.x;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int g = find_graph(starts, nG, item);
         const GDev &d = G[g];
@@ -502,90 +688,10 @@ __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restric
         }
         int m = 2;
         while (m < k) m <<= 1;
-        int ell = 0;
-        for (int j = tid; j < m; j += HUB_THREADS) {
-            int key = KEY_PAD;
-            if (j < k) {
-                const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
-                if (u == v) {
-                    if (j < kout) ++ell;
-                } else {
-                    key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
-                }
-            }
-            Kg[j] = key;
-        }
-        ell = wave_sum_i32(ell);
-        if (lane == 0) red[wv] = ell;
-        __threadfence_block();
-        __syncthreads();
-        if (tid == 0) {
-            int t = 0;
-            for (int w = 0; w < HUB_THREADS / 64; ++w) t += red[w];
-            s_ell = t;
-        }
-        for (int size = 2; size <= m; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int q = tid; q < (m >> 1); q += HUB_THREADS) {
-                    const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
-                    const bool asc = (i & size) == 0;
-                    const int a = Kg[i], b = Kg[j];
-                    if ((a > b) == asc) {
-                        Kg[i] = b;
-                        Kg[j] = a;
-                    }
-                }
-                __threadfence_block();
-                __syncthreads();
-            }
-        }
-        ell = s_ell;
-        const int kk = k - 2 * ell;
-        // run starts, in order, by wave 0 scanning 64 positions at a time
-        if (wv == 0) {
-            int D = 0;
-            int pend_idx = -1, pend_p = 0, pend_key = 0, evens = 0, pend_evens = 0;
-            for (int base = 0; base < kk; base += 64) {
-                const int p = base + lane;
-                const int key = p < kk ? Kg[p] : KEY_PAD;
-                const int prev = (p > 0 && p < kk) ? Kg[p - 1] : -2;
-                const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
-                const bool ev = p < kk && !(key & 1);
-                const uint64_t sm = __ballot(st), em = __ballot(ev);
-                // close runs: every start in this chunk ends the previous run
-                uint64_t rest = sm;
-                while (rest) {
-                    const int b = __builtin_ctzll(rest);
-                    rest &= rest - 1;
-                    const int pos = base + b;
-                    const int ev_before = evens + __popcll(em & ((b ? (~0ull >> (64 - b)) : 0ull)));
-                    if (pend_idx >= 0 && lane == 0) {
-                        const int ko = ev_before - pend_evens;
-                        Dt[pend_idx] = pend_key >> 1;
-                        Dko[pend_idx] = ko;
-                        Dki[pend_idx] = (pos - pend_p) - ko;
-                    }
-                    pend_idx = D++;
-                    pend_p = pos;
-                    pend_key = __shfl(key, b, SBP_WAVE);
-                    pend_evens = ev_before;
-                }
-                evens += __popcll(em);
-            }
-            if (pend_idx >= 0 && lane == 0) {
-                const int ko = evens - pend_evens;
-                Dt[pend_idx] = pend_key >> 1;
-                Dko[pend_idx] = ko;
-                Dki[pend_idx] = (kk - pend_p) - ko;
-            }
-            if (lane == 0) s_D = D;
-        }
-        __threadfence_block();
-        __syncthreads();
-        if (wv == 0) {
-            const MoveOut o = move_terms(d, bm, r, s, Dt, Dko, Dki, s_D, ell, kout, kin, lnu);
-            if (lane == 0) record_move(d, v, r, o, false, nb, tr);
-        }
+        if (m <= HUB_LDS)
+            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, lnu, Ks, Dts, Dks, nb, tr, red, &s_ell, &s_D, red_d, red_i);
+        else
+            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, lnu, Kg, Dtg, Dkg, nb, tr, red, &s_ell, &s_D, red_d, red_i);
         __syncthreads();
     }
 }
