@@ -168,22 +168,30 @@ __global__ void __launch_bounds__(256) k_sweep_stats_part(const signed char *__r
         sum_part[blockIdx.x] = t;
     }
 }
-__global__ void k_sweep_stats_final(const long long *__restrict__ part, const double *__restrict__ sum_part, int nblk,
-                                    const double *__restrict__ dl, sbp_sweep_stats_dev *__restrict__ st) {
-    if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) k_sweep_stats_final(const long long *__restrict__ part,
+                                                          const double *__restrict__ sum_part, int nblk,
+                                                          const double *__restrict__ dl,
+                                                          sbp_sweep_stats_dev *__restrict__ st) {
+    const int lane = threadIdx.x;
     long long p = 0, q = 0, r = 0;
     double t = 0.0;
-    for (int w = 0; w < nblk; ++w) {
+    for (int w = lane; w < nblk; w += 64) {
         p += part[4 * w + 0];
         q += part[4 * w + 1];
         r += part[4 * w + 2];
         t += sum_part[w];
     }
-    st->proposals += p;
-    st->self_proposals += q;
-    st->accepted += r;
-    st->sum_dS_accepted += t;
-    if (dl) st->dl_after = *dl;
+    p = wave_sum_i64(p);
+    q = wave_sum_i64(q);
+    r = wave_sum_i64(r);
+    t = wave_sum(t);
+    if (lane == 0) {
+        st->proposals += p;
+        st->self_proposals += q;
+        st->accepted += r;
+        st->sum_dS_accepted += t;
+        if (dl) st->dl_after = *dl;
+    }
 }
 __global__ void k_copy_dl(const double *__restrict__ src, double *__restrict__ dst) { *dst = *src; }
 __global__ void k_relabel_map(int *__restrict__ lab, const int *__restrict__ map, int n) {

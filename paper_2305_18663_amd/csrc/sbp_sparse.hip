@@ -226,15 +226,20 @@ __global__ void __launch_bounds__(BLK) k_dl_partial(const GDev *__restrict__ G, 
     }
 }
 
-__global__ void k_dl_final(const GDev *__restrict__ G, const int *__restrict__ chstart, int nG, int nchunks,
-                           const double *__restrict__ part, double *__restrict__ dl) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// DL of every graph from its chunk partials: a wave per graph, lane l adding
+// the graph's partials l, l + 64, ... (counted from the graph's first chunk),
+// so the sum does not depend on the other graphs of a batch.
+__global__ void __launch_bounds__(64) k_dl_final(const GDev *__restrict__ G, const int *__restrict__ chstart, int nG,
+                                                 int nchunks, const double *__restrict__ part,
+                                                 double *__restrict__ dl) {
+    const int g = blockIdx.x, lane = threadIdx.x;
     if (g >= nG) return;
     const GDev &d = G[g];
     const int c0 = chstart[g], c1 = g + 1 < nG ? chstart[g + 1] : nchunks;
     double L = 0.0;
-    for (int c = c0; c < c1; ++c) L += part[c];
-    dl[g] = model_terms((double)d.e, (double)d.n, (double)d.C) - L;
+    for (int c = c0 + lane; c < c1; c += 64) L += part[c];
+    L = wave_sum(L);
+    if (lane == 0) dl[g] = model_terms((double)d.e, (double)d.n, (double)d.C) - L;
 }
 
 // ---------------------------------------------------------------- vertex moves
@@ -341,12 +346,102 @@ __device__ __forceinline__ void record_move(const GDev &d, int v, int r, const M
 constexpr int LEAF_WAVES = 4;
 constexpr int KEY_PAD = 0x7fffffff;
 
+// Row r, row s, column r and column s of M for one move, staged in LDS by
+// the wave when at most LEAF_ROW long (else looked up in global memory): list
+// l holds (index, value) pairs ascending by index.
+constexpr int LEAF_ROW = 128;
+struct MoveLists {
+    const int *sc, *sv;  // the wave's staged lists: list l at l * LEAF_ROW
+    int b0[4], len[4];   // first entry in the global rows (l < 2) or columns, length
+};
+template <int l>
+__device__ __forceinline__ int list_get(const SparseBM &bm, const MoveLists &L, int b) {
+    const int n = L.len[l];
+    const bool staged = n <= LEAF_ROW;
+    const int *c = staged ? L.sc + l * LEAF_ROW : (l < 2 ? bm.rcol : bm.crow) + L.b0[l];
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= n || c[lo] != b) return 0;
+    return staged ? L.sv[l * LEAF_ROW + lo] : (l < 2 ? bm.rval : bm.cval)[L.b0[l] + lo];
+}
+
+// move_terms with the four lists of the move: M_rt from row r, M_st from row
+// s, M_tr from column r, M_ts from column s.
+__device__ MoveOut move_terms_lists(const GDev &d, const SparseBM &bm, const MoveLists &ML, int r, int s,
+                                    const int *dt, const int *dko, const int *dki, int D, int ell, int kout, int kin,
+                                    double lnu) {
+    const int lane = threadIdx.x & 63;
+    const double eps = (double)d.eps;
+    const double epsC = (double)d.eps * (double)d.C;
+    double dL = 0.0, qf = 0.0, qr = 0.0;
+    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
+    for (int i = lane; i < D; i += 64) {
+        const int t = dt[i], ko = dko[i], ki = dki[i];
+        if (t == r) {
+            ko_r = ko;
+            ki_r = ki;
+            continue;
+        }
+        if (t == s) {
+            ko_s = ko;
+            ki_s = ki;
+            continue;
+        }
+        const int Mrt = list_get<0>(bm, ML, t), Mst = list_get<1>(bm, ML, t);
+        const int Mtr = list_get<2>(bm, ML, t), Mts = list_get<3>(bm, ML, t);
+        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
+        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
+        const double kt = (double)(ko + ki);
+        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
+        qf += kt * (((double)(Mts + Mst) + eps) / den);
+        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+    }
+    ko_r = wave_sum_i32(ko_r);
+    ki_r = wave_sum_i32(ki_r);
+    ko_s = wave_sum_i32(ko_s);
+    ki_s = wave_sum_i32(ki_s);
+    if (lane == 0) {
+        const int Mrr = list_get<0>(bm, ML, r), Mrs = list_get<0>(bm, ML, s), Msr = list_get<1>(bm, ML, r), Mss = list_get<1>(bm, ML, s);
+        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
+        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
+        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
+        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
+        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
+        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
+        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
+        const double k = (double)(kout + kin);
+        const double d_r = dor + dir, d_s = dos + dis;
+        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
+        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
+        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
+        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
+        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
+        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
+    }
+    dL = wave_sum(dL);
+    qf = wave_sum(qf);
+    qr = wave_sum(qr);
+    MoveOut o;
+    o.s = s;
+    o.dS = -dL;
+    o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
+    const double z = -d.beta * o.dS + o.lnH;
+    o.margin = z - lnu;
+    o.accept = lnu < z;
+    return o;
+}
+
 // Wave per vertex with at most 256 edge ends.
 __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__restrict__ G, const int *__restrict__ starts,
                                                                int nG, int n_items, SparseBM bm, int *__restrict__ nb,
                                                                SweepTraceDev tr) {
     __shared__ int K[LEAF_WAVES][SBP_LEAF_MAX];
     __shared__ int Dt[LEAF_WAVES][SBP_LEAF_MAX], Dko[LEAF_WAVES][SBP_LEAF_MAX], Dki[LEAF_WAVES][SBP_LEAF_MAX];
+    __shared__ int SC[LEAF_WAVES][4 * LEAF_ROW], SV[LEAF_WAVES][4 * LEAF_ROW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int gw = blockIdx.x * LEAF_WAVES + wv, nw = gridDim.x * LEAF_WAVES;
     int *Kw = K[wv];
@@ -369,6 +464,28 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
             o.s = s;
             if (lane == 0) record_move(d, v, r, o, true, nb, tr);
             continue;
+        }
+        // rows r, s and columns r, s of M, loaded while the keys are built
+        MoveLists ML;
+        ML.sc = SC[wv];
+        ML.sv = SV[wv];
+        {
+            const int rs[4] = {r, s, r, s};
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int *ptr = l < 2 ? bm.rptr : bm.cptr;
+                ML.b0[l] = ptr[rs[l]];
+                ML.len[l] = ptr[rs[l] + 1] - ML.b0[l];
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+                if (ML.len[l] <= LEAF_ROW) {
+                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + ML.b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + ML.b0[l];
+                    for (int j = lane; j < ML.len[l]; j += 64) {
+                        SC[wv][l * LEAF_ROW + j] = gc[j];
+                        SV[wv][l * LEAF_ROW + j] = gv[j];
+                    }
+                }
         }
         // edge-end keys 2 t + dir; self-loop ends and padding sort last
         int ell = 0;
@@ -456,7 +573,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
             Dki[wv][idx] = (end - p) - ko;
         }
         wave_sync_lds();
-        const MoveOut o = move_terms(d, bm, r, s, Dt[wv], Dko[wv], Dki[wv], D, ell, kout, kin, lnu);
+        const MoveOut o = move_terms_lists(d, bm, ML, r, s, Dt[wv], Dko[wv], Dki[wv], D, ell, kout, kin, lnu);
         if (lane == 0) record_move(d, v, r, o, false, nb, tr);
         wave_sync_lds();
     }
@@ -1005,7 +1122,7 @@ int union_dl(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch
     if (m.n_chunks > 0)
         hipLaunchKernelGGL(k_dl_partial, dim3(m.n_chunks), dim3(BLK), 0, s, dG, m.chstart, m.G, m.n_chunks, bm,
                            ws.dl_part);
-    hipLaunchKernelGGL(k_dl_final, dim3((m.G + 63) / 64), dim3(64), 0, s, dG, m.chstart, m.G, m.n_chunks, ws.dl_part,
+    hipLaunchKernelGGL(k_dl_final, dim3(m.G), dim3(64), 0, s, dG, m.chstart, m.G, m.n_chunks, ws.dl_part,
                        ws.dl);
     SBP_LAUNCH_CHECK();
     return 0;
