@@ -95,6 +95,23 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
+// A DPP move of a double: both halves with the same control.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// Sum over an aligned group of 8 lanes (half a DPP row): pairs, quads, then
+// the mirrored half.  Each step adds the same two values on every lane, so the
+// whole group ends with one identical sum.
+__device__ __forceinline__ double grp8_sum(double x) {
+    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141>(x);  // row_half_mirror
+    return x;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -870,10 +870,93 @@ __device__ double merge_dL(const SparseBM &bm, int A, int B) {
     return wave_sum(acc);
 }
 
+// merge_dL with row A and column A of M staged in LDS (ac/av: columns and
+// values of row A, la entries; rc/rv: rows and values of column A, lc
+// entries): the wave walks row B and column B in global memory and finds the
+// matching entries of A in LDS.  The same terms as merge_dL.
+constexpr int MERGE_ROW = 256;
+__device__ __forceinline__ int lds_find(const int *__restrict__ c, const int *__restrict__ v, int n, int b) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && c[lo] == b) ? v[lo] : 0;
+}
+__device__ double merge_dL_staged(const SparseBM &bm, int A, int B, const int *ac, const int *av, int la,
+                                  const int *rc, const int *rv, int lc) {
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int q = bm.rptr[B] + lane; q < bm.rptr[B + 1]; q += 64) {
+        const int t = bm.rcol[q];
+        if (t == A || t == B) continue;
+        const int x = lds_find(ac, av, la, t);
+        if (x) {
+            const int y = bm.rval[q];
+            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+        }
+    }
+    for (int q = bm.cptr[B] + lane; q < bm.cptr[B + 1]; q += 64) {
+        const int t = bm.crow[q];
+        if (t == A || t == B) continue;
+        const int x = lds_find(rc, rv, lc, t);
+        if (x) {
+            const int y = bm.cval[q];
+            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+        }
+    }
+    if (lane == 0) {
+        const int a = lds_find(ac, av, la, A), b = lds_find(ac, av, la, B), e = lds_find(rc, rv, lc, B);
+        const int g = m_get(bm, B, B);
+        acc += xlogx((double)(a + b + e + g)) - xlogx((double)a) - xlogx((double)b) - xlogx((double)e) -
+               xlogx((double)g);
+        const double oa = bm.dout[A], ob = bm.dout[B], ia = bm.din[A], ib = bm.din[B];
+        acc -= xlogx(oa + ob) - xlogx(oa) - xlogx(ob);
+        acc -= xlogx(ia + ib) - xlogx(ia) - xlogx(ib);
+    }
+    return wave_sum(acc);
+}
+
+// merge_dL_staged evaluated by an aligned group of 8 lanes (gl = lane in the
+// group), each group with its own B; every lane of the group ends with the sum.
+__device__ double merge_dL_grp8(const SparseBM &bm, int A, int B, const int *ac, const int *av, int la,
+                                const int *rc, const int *rv, int lc, int gl) {
+    double acc = 0.0;
+    for (int q = bm.rptr[B] + gl; q < bm.rptr[B + 1]; q += 8) {
+        const int t = bm.rcol[q];
+        if (t == A || t == B) continue;
+        const int x = lds_find(ac, av, la, t);
+        if (x) {
+            const int y = bm.rval[q];
+            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+        }
+    }
+    for (int q = bm.cptr[B] + gl; q < bm.cptr[B + 1]; q += 8) {
+        const int t = bm.crow[q];
+        if (t == A || t == B) continue;
+        const int x = lds_find(rc, rv, lc, t);
+        if (x) {
+            const int y = bm.cval[q];
+            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
+        }
+    }
+    if (gl == 0) {
+        const int a = lds_find(ac, av, la, A), b = lds_find(ac, av, la, B), e = lds_find(rc, rv, lc, B);
+        const int g = m_get(bm, B, B);
+        acc += xlogx((double)(a + b + e + g)) - xlogx((double)a) - xlogx((double)b) - xlogx((double)e) -
+               xlogx((double)g);
+        const double oa = bm.dout[A], ob = bm.dout[B], ia = bm.din[A], ib = bm.din[B];
+        acc -= xlogx(oa + ob) - xlogx(oa) - xlogx(ob);
+        acc -= xlogx(ia + ib) - xlogx(ia) - xlogx(ib);
+    }
+    return grp8_sum(acc);
+}
+
 __global__ void __launch_bounds__(BLK) k_merge_scores(const GDev *__restrict__ G, const int *__restrict__ bstart, int nG,
                                                      int n_items, SparseBM bm, int *__restrict__ partner,
                                                      double *__restrict__ dS, double *__restrict__ dSl) {
-    const int lane = threadIdx.x & 63;
+    __shared__ int sAc[BLK / 64][MERGE_ROW], sAv[BLK / 64][MERGE_ROW], sRc[BLK / 64][MERGE_ROW], sRv[BLK / 64][MERGE_ROW];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
     for (int item = gw; item < n_items; item += nw) {
         const int g = find_graph(bstart, nG, item);
@@ -886,22 +969,68 @@ __global__ void __launch_bounds__(BLK) k_merge_scores(const GDev *__restrict__ G
         int best = -1;
         double bestL = 0.0;
         long long bestkey = INT64_MAX;
-        for (int j = 0; j < d.proposals && C > 1; ++j) {
+        // row A and column A in LDS when short enough, for all the proposals
+        const int ra = bm.rptr[A], la = bm.rptr[A + 1] - ra, ca = bm.cptr[A], lc = bm.cptr[A + 1] - ca;
+        const bool staged = la <= MERGE_ROW && lc <= MERGE_ROW;
+        if (staged) {
+            for (int q = lane; q < la; q += 64) {
+                sAc[wv][q] = bm.rcol[ra + q];
+                sAv[wv][q] = bm.rval[ra + q];
+            }
+            for (int q = lane; q < lc; q += 64) {
+                sRc[wv][q] = bm.crow[ca + q];
+                sRv[wv][q] = bm.cval[ca + q];
+            }
+        }
+        wave_sync_lds();
+        // the partners of 64 proposals at a time: lane l draws proposal j0 + l
+        for (int j0 = 0; j0 < d.proposals && C > 1; j0 += 64) {
+        int cp_lane = c;
+        if (j0 + lane < d.proposals) {
+            const int j = j0 + lane;
             const Words4 W = draw_words(d.seed, (uint32_t)c, d.phase, (uint32_t)(2 * j), 1u);
-            int cp;
             if (dc == 0) {
                 const int kk = (int)draw_idx(W.w[2], (uint64_t)(C - 1));
-                cp = kk + (kk >= c);
+                cp_lane = kk + (kk >= c);
             } else {
                 const int t = s_draw(bm, A, draw_idx(W.w[0], (uint64_t)dc));
                 const long long dt = (long long)bm.dout[t] + bm.din[t];
                 if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) {
                     const int kk = (int)draw_idx(W.w[2], (uint64_t)(C - 1));
-                    cp = kk + (kk >= c);
+                    cp_lane = kk + (kk >= c);
                 } else {
-                    cp = s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt)) - d.boff;
+                    cp_lane = s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt)) - d.boff;
                 }
             }
+        }
+        const int n_here = d.proposals - j0 < 64 ? d.proposals - j0 : 64;
+        if (staged) {
+            // eight proposals at a time, one per group of 8 lanes; then taken
+            // in proposal order
+            const int gl = lane & 7, grp = lane >> 3;
+            for (int jb = 0; jb < n_here; jb += 8) {
+                const int jj = jb + grp;
+                const int cpg = __shfl(cp_lane, jj < n_here ? jj : 0, SBP_WAVE);
+                const bool ok = jj < n_here && cpg != c;
+                const double lg = -merge_dL_grp8(bm, A, d.boff + (ok ? cpg : c), sAc[wv], sAv[wv], la, sRc[wv],
+                                                 sRv[wv], lc, gl);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int cp = __shfl(cpg, 8 * q, SBP_WAVE);
+                    const double local = __shfl(lg, 8 * q, SBP_WAVE);
+                    if (jb + q >= n_here || cp == c) continue;
+                    const long long key = merge_rank(local);
+                    if (key < bestkey) {
+                        bestkey = key;
+                        best = cp;
+                        bestL = local;
+                    }
+                }
+            }
+            continue;
+        }
+        for (int jj = 0; jj < n_here; ++jj) {
+            const int cp = __shfl(cp_lane, jj, SBP_WAVE);
             if (cp == c) continue;
             const double local = -merge_dL(bm, A, d.boff + cp);
             const long long key = merge_rank(local);
@@ -910,6 +1039,7 @@ __global__ void __launch_bounds__(BLK) k_merge_scores(const GDev *__restrict__ G
                 best = cp;
                 bestL = local;
             }
+        }
         }
         if (lane == 0) {
             const double inf = __builtin_huge_val();
@@ -920,6 +1050,7 @@ __global__ void __launch_bounds__(BLK) k_merge_scores(const GDev *__restrict__ G
                                      : 0.0;
             dS[d.boff + c] = best < 0 ? inf : bestL + off;
         }
+        wave_sync_lds();
     }
 }
 
