@@ -56,16 +56,38 @@ __device__ __forceinline__ double model_terms(double E, double N, double C) {
 }
 
 // ---------------------------------------------------------------- build
-__global__ void k_edge_keys(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG, int Ntot, int Ctot,
-                            uint64_t *__restrict__ keys) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Ntot; i += gridDim.x * blockDim.x) {
-        const int g = find_graph(vstart, nG, i);
-        const GDev &d = G[g];
-        const int v = i - d.voff;
-        const uint64_t base = (uint64_t)(d.boff + d.lab[v]) * (uint64_t)Ctot + (uint64_t)d.boff;
-        const int j0 = d.out_ptr[v], j1 = d.out_ptr[v + 1];
-        uint64_t *out = keys + d.eoff;
-        for (int j = j0; j < j1; ++j) out[j] = base + (uint64_t)d.lab[d.out_idx[j]];
+// Workgroup per BLK consecutive union vertices: their union edge ranges and
+// source keys go to LDS, then the workgroup's threads take the edges in order,
+// each finding its source vertex there, so hubs do not serialise a thread.
+__global__ void __launch_bounds__(BLK) k_edge_keys(const GDev *__restrict__ G, const int *__restrict__ vstart,
+                                                   int nG, int Ntot, int Ctot, uint64_t *__restrict__ keys) {
+    __shared__ long long U[BLK + 1];  // union edge start of each vertex, then the end of the last
+    __shared__ uint64_t base[BLK];
+    __shared__ int gi[BLK];
+    for (int b0 = blockIdx.x * BLK; b0 < Ntot; b0 += gridDim.x * BLK) {
+        const int nv = min(BLK, Ntot - b0);
+        __syncthreads();  // previous range done with the LDS
+        if ((int)threadIdx.x < nv) {
+            const int t = threadIdx.x, i = b0 + t;
+            const int g = find_graph(vstart, nG, i);
+            const GDev &d = G[g];
+            const int v = i - d.voff;
+            U[t] = d.eoff + d.out_ptr[v];
+            base[t] = (uint64_t)(d.boff + d.lab[v]) * (uint64_t)Ctot + (uint64_t)d.boff;
+            gi[t] = g;
+            if (t == nv - 1) U[nv] = d.eoff + d.out_ptr[v + 1];
+        }
+        __syncthreads();
+        const long long e1 = U[nv];
+        for (long long x = U[0] + threadIdx.x; x < e1; x += BLK) {
+            int lo = 0, hi = nv - 1;  // last vertex whose range starts at or before x
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (U[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            const GDev &d = G[gi[lo]];
+            keys[x] = base[lo] + (uint64_t)d.lab[d.out_idx[x - d.eoff]];
+        }
     }
 }
 
@@ -263,73 +285,6 @@ __device__ __forceinline__ int propose(const GDev &d, const SparseBM &bm, int v,
     return s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt));
 }
 
-// DL change and Hastings term of moving v from r to s (union ids), given the
-// distinct neighbour blocks (ascending) with out/in edge counts; evaluated by
-// one wave, identical on every lane afterwards.
-__device__ MoveOut move_terms(const GDev &d, const SparseBM &bm, int r, int s, const int *dt, const int *dko,
-                              const int *dki, int D, int ell, int kout, int kin, double lnu) {
-    const int lane = threadIdx.x & 63;
-    const double eps = (double)d.eps;
-    const double epsC = (double)d.eps * (double)d.C;
-    double dL = 0.0, qf = 0.0, qr = 0.0;
-    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
-    for (int i = lane; i < D; i += 64) {
-        const int t = dt[i], ko = dko[i], ki = dki[i];
-        if (t == r) {
-            ko_r = ko;
-            ki_r = ki;
-            continue;
-        }
-        if (t == s) {
-            ko_s = ko;
-            ki_s = ki;
-            continue;
-        }
-        const int Mrt = m_get(bm, r, t), Mst = m_get(bm, s, t);
-        const int Mtr = m_get(bm, t, r), Mts = m_get(bm, t, s);
-        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
-        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
-        const double kt = (double)(ko + ki);
-        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
-        qf += kt * (((double)(Mts + Mst) + eps) / den);
-        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
-    }
-    ko_r = wave_sum_i32(ko_r);
-    ki_r = wave_sum_i32(ki_r);
-    ko_s = wave_sum_i32(ko_s);
-    ki_s = wave_sum_i32(ki_s);
-    if (lane == 0) {
-        const int Mrr = m_get(bm, r, r), Mrs = m_get(bm, r, s), Msr = m_get(bm, s, r), Mss = m_get(bm, s, s);
-        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
-        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
-        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
-        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
-        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
-        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
-        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
-        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
-        const double k = (double)(kout + kin);
-        const double d_r = dor + dir, d_s = dos + dis;
-        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
-        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
-        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
-        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
-        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
-        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
-    }
-    dL = wave_sum(dL);
-    qf = wave_sum(qf);
-    qr = wave_sum(qr);
-    MoveOut o;
-    o.s = s;
-    o.dS = -dL;
-    o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
-    const double z = -d.beta * o.dS + o.lnH;
-    o.margin = z - lnu;
-    o.accept = lnu < z;
-    return o;
-}
-
 __device__ __forceinline__ void record_move(const GDev &d, int v, int r, const MoveOut &o, bool noop, int *nb,
                                             const SweepTraceDev &tr) {
     const int u = d.voff + v;
@@ -345,237 +300,543 @@ __device__ __forceinline__ void record_move(const GDev &d, int v, int r, const M
 
 constexpr int LEAF_WAVES = 4;
 constexpr int KEY_PAD = 0x7fffffff;
+constexpr int KEY_SELF = 0x7ffffffe;  // self-loop end: after every block key, before the padding
 
-// Row r, row s, column r and column s of M for one move, staged in LDS by
-// the wave when at most LEAF_ROW long (else looked up in global memory): list
-// l holds (index, value) pairs ascending by index.
+constexpr int SMALL_K = 16;  // vertices with at most this many edge ends go four to a wave
+
+// Whether flat sweep item i is a vertex of the current batch with kmin..kmax
+// edge ends.
+__device__ __forceinline__ bool sweep_item(const GDev *G, const int *starts, int nG, int n_items, int i, int kmin,
+                                           int kmax) {
+    if (i >= n_items) return false;
+    const int g = find_graph(starts, nG, i);
+    const GDev &d = G[g];
+    const int v = i - starts[g];
+    const int k = d.out_ptr[v + 1] - d.out_ptr[v] + d.in_ptr[v + 1] - d.in_ptr[v];
+    return (v % d.n_batches) == d.batch && k >= kmin && k <= kmax;
+}
+
+// s_draw by a whole wave: each round probes 64 evenly spaced running sums and
+// keeps the stretch between the last probe at or below x and the first above.
+__device__ __forceinline__ int s_draw_wave(const SparseBM &bm, int t, long long x) {
+    const int lane = threadIdx.x & 63;
+    int lo = bm.rptr[t] + bm.cptr[t], hi = bm.rptr[t + 1] + bm.cptr[t + 1];  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int st = (hi - lo + 63) >> 6;
+        const int p = min(lo + (lane + 1) * st, hi) - 1;  // the last probe is hi - 1, whose sum d_t exceeds x
+        const int f = __builtin_ctzll(__ballot((long long)bm.scum[p] > x));
+        const int nlo = min(lo + f * st, hi);
+        hi = min(lo + (f + 1) * st, hi);
+        lo = nlo;
+    }
+    return bm.scol[lo];
+}
+
+// Row r, row s, column r and column s of M for one move: list l holds
+// (index, value) pairs ascending by index, staged in the wave's LDS when at
+// most LEAF_ROW long, else read in place.
 constexpr int LEAF_ROW = 128;
 struct MoveLists {
-    const int *sc, *sv;  // the wave's staged lists: list l at l * LEAF_ROW
-    int b0[4], len[4];   // first entry in the global rows (l < 2) or columns, length
+    const int *c[4], *v[4];
+    int n[4];
 };
-template <int l>
-__device__ __forceinline__ int list_get(const SparseBM &bm, const MoveLists &L, int b) {
-    const int n = L.len[l];
-    const bool staged = n <= LEAF_ROW;
-    const int *c = staged ? L.sc + l * LEAF_ROW : (l < 2 ? bm.rcol : bm.crow) + L.b0[l];
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (c[mid] < b) lo = mid + 1; else hi = mid;
+
+// The entries at index t of the four lists (0 where absent): lower-bound
+// searches by descending powers of two, run side by side so that every step
+// issues one load per list and the four share their round trips.
+__device__ __forceinline__ void lists_lookup(const MoveLists &L, int nmax, int t, int out[4]) {
+    int lo[4] = {0, 0, 0, 0};
+    for (int st = nmax > 0 ? 1 << (31 - __clz(nmax)) : 0; st > 0; st >>= 1) {
+        int kv[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) kv[l] = L.n[l] > 0 ? L.c[l][min(lo[l] + st, L.n[l]) - 1] : 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            if (lo[l] + st <= L.n[l] && kv[l] < t) lo[l] += st;
     }
-    if (lo >= n || c[lo] != b) return 0;
-    return staged ? L.sv[l * LEAF_ROW + lo] : (l < 2 ? bm.rval : bm.cval)[L.b0[l] + lo];
+    int kv[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) kv[l] = lo[l] < L.n[l] ? L.c[l][lo[l]] : -1;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[l] = kv[l] == t ? L.v[l][lo[l]] : 0;
 }
 
-// move_terms with the four lists of the move: M_rt from row r, M_st from row
-// s, M_tr from column r, M_ts from column s.
-__device__ MoveOut move_terms_lists(const GDev &d, const SparseBM &bm, const MoveLists &ML, int r, int s,
-                                    const int *dt, const int *dko, const int *dki, int D, int ell, int kout, int kin,
-                                    double lnu) {
-    const int lane = threadIdx.x & 63;
-    const double eps = (double)d.eps;
-    const double epsC = (double)d.eps * (double)d.C;
-    double dL = 0.0, qf = 0.0, qr = 0.0;
-    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
-    for (int i = lane; i < D; i += 64) {
-        const int t = dt[i], ko = dko[i], ki = dki[i];
-        if (t == r) {
-            ko_r = ko;
-            ki_r = ki;
-            continue;
-        }
-        if (t == s) {
-            ko_s = ko;
-            ki_s = ki;
-            continue;
-        }
-        const int Mrt = list_get<0>(bm, ML, t), Mst = list_get<1>(bm, ML, t);
-        const int Mtr = list_get<2>(bm, ML, t), Mts = list_get<3>(bm, ML, t);
-        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
-        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
-        const double kt = (double)(ko + ki);
-        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
-        qf += kt * (((double)(Mts + Mst) + eps) / den);
-        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
-    }
-    ko_r = wave_sum_i32(ko_r);
-    ki_r = wave_sum_i32(ki_r);
-    ko_s = wave_sum_i32(ko_s);
-    ki_s = wave_sum_i32(ki_s);
-    if (lane == 0) {
-        const int Mrr = list_get<0>(bm, ML, r), Mrs = list_get<0>(bm, ML, s), Msr = list_get<1>(bm, ML, r), Mss = list_get<1>(bm, ML, s);
-        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
-        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
-        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
-        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
-        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
-        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
-        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
-        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
-        const double k = (double)(kout + kin);
-        const double d_r = dor + dir, d_s = dos + dis;
-        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
-        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
-        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
-        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
-        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
-        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
-    }
-    dL = wave_sum(dL);
-    qf = wave_sum(qf);
-    qr = wave_sum(qr);
-    MoveOut o;
-    o.s = s;
-    o.dS = -dL;
-    o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
-    const double z = -d.beta * o.dS + o.lnH;
-    o.margin = z - lnu;
-    o.accept = lnu < z;
-    return o;
+// DL and proposal terms of one distinct neighbour block t other than r and
+// s: Mv = (M_rt, M_st, M_tr, M_ts), ko / ki the out / in ends of v into t,
+// dtt = d_t.
+__device__ __forceinline__ void block_terms(int ko, int ki, const int Mv[4], long long dtt, double eps, double epsC,
+                                            double &dL, double &qf, double &qr) {
+    const int Mrt = Mv[0], Mst = Mv[1], Mtr = Mv[2], Mts = Mv[3];
+    if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
+    if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
+    const double kt = (double)(ko + ki);
+    const double den = (double)dtt + epsC;
+    qf += kt * (((double)(Mts + Mst) + eps) / den);
+    qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
 }
 
-// Wave per vertex with at most 256 edge ends.
+// Term cl of the blocks r and s themselves, one per lane: 0-3 the corner
+// entries rr, rs, sr, ss; 4-7 the block degrees (opposite sign); 8-9 the
+// forward and 10-11 the reverse proposal weights of r and s.  kpr / kps pack
+// v's out | in << 16 ends into r / s.
+struct CornerIn {
+    int Mrr, Mrs, Msr, Mss, kpr, kps, ell, kout, kin, dor, dos, dir, dis;
+};
+__device__ __forceinline__ void corner_term(int cl, const CornerIn &c, double eps, double epsC, double &dL, double &qf,
+                                            double &qr) {
+    const int ko_r = c.kpr & 0xffff, ki_r = c.kpr >> 16, ko_s = c.kps & 0xffff, ki_s = c.kps >> 16;
+    const int drr = -ko_r - ki_r - c.ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + c.ell;
+    if (cl < 8) {
+        double x, y;
+        switch (cl) {
+            case 0: x = c.Mrr + drr, y = c.Mrr; break;
+            case 1: x = c.Mrs + drs, y = c.Mrs; break;
+            case 2: x = c.Msr + dsr, y = c.Msr; break;
+            case 3: x = c.Mss + dss, y = c.Mss; break;
+            case 4: x = c.dor - c.kout, y = c.dor; break;
+            case 5: x = c.dos + c.kout, y = c.dos; break;
+            case 6: x = c.dir - c.kin, y = c.dir; break;
+            default: x = c.dis + c.kin, y = c.dis; break;
+        }
+        const double f = xlogx(x) - xlogx(y);
+        dL += cl < 4 ? f : -f;
+    } else if (cl < 12) {
+        const double kd = (double)(c.kout + c.kin);
+        const double d_r = (double)c.dor + (double)c.dir, d_s = (double)c.dos + (double)c.dis;
+        int w, num;
+        double den;
+        switch (cl) {
+            case 8: w = ko_r + ki_r + 2 * c.ell, num = c.Mrs + c.Msr, den = d_r + epsC; break;
+            case 9: w = ko_s + ki_s, num = 2 * c.Mss, den = d_s + epsC; break;
+            case 10: w = ko_r + ki_r, num = 2 * (c.Mrr + drr), den = d_r - kd + epsC; break;
+            default: w = ko_s + ki_s + 2 * c.ell, num = c.Msr + dsr + c.Mrs + drs, den = d_s + kd + epsC; break;
+        }
+        if (w) {
+            const double q = (double)w * (((double)num + eps) / den);
+            if (cl < 10) qf += q; else qr += q;
+        }
+    }
+}
+
+// Wave per vertex with at most SBP_LEAF_MAX edge ends.  The edge-end keys are
+// gathered first (one to four per lane), so the proposal reads the drawn end's
+// block from a register; keys are sorted in registers when they fit one per
+// lane.  The distinct neighbour blocks, with r and s always among them, take
+// their four M entries from one interleaved search each; the lanes holding r
+// and s publish the corner entries, and the corner, degree and Hastings terms
+// of r and s are spread over lanes 0..11 before the three wave sums.
 __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__restrict__ G, const int *__restrict__ starts,
                                                                int nG, int n_items, SparseBM bm, int *__restrict__ nb,
                                                                SweepTraceDev tr) {
     __shared__ int K[LEAF_WAVES][SBP_LEAF_MAX];
-    __shared__ int Dt[LEAF_WAVES][SBP_LEAF_MAX], Dko[LEAF_WAVES][SBP_LEAF_MAX], Dki[LEAF_WAVES][SBP_LEAF_MAX];
+    __shared__ int Dt[LEAF_WAVES][SBP_LEAF_MAX], PE[LEAF_WAVES][SBP_LEAF_MAX + 1];
     __shared__ int SC[LEAF_WAVES][4 * LEAF_ROW], SV[LEAF_WAVES][4 * LEAF_ROW];
+    __shared__ int CV[LEAF_WAVES][8];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gw = blockIdx.x * LEAF_WAVES + wv, nw = gridDim.x * LEAF_WAVES;
+    const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * LEAF_WAVES + wv), nw = gridDim.x * LEAF_WAVES;
     int *Kw = K[wv];
     const uint64_t below = lanemask_lt();
-    for (int item = gw; item < n_items; item += nw) {
-        const int g = find_graph(starts, nG, item);
-        const GDev &d = G[g];
-        const int v = item - starts[g];
-        if ((v % d.n_batches) != d.batch) continue;
-        if (d.out_ptr[v + 1] - d.out_ptr[v] + d.in_ptr[v + 1] - d.in_ptr[v] > SBP_LEAF_MAX) continue;
-        const int r = d.boff + d.lab[v];
-        const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
-        const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
-        const int k = kout + kin;
-        const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
-        const double lnu = log(draw_unit(W.w[3]));
-        const int s = propose(d, bm, v, r, kout, kin, W);
-        if (s == r) {
+    for (int tile = gw * 64; tile < n_items; tile += nw * 64) {
+        const uint64_t mine = __ballot(sweep_item(G, starts, nG, n_items, tile + lane, SMALL_K + 1, SBP_LEAF_MAX));
+        for (uint64_t todo = mine; todo; todo &= todo - 1) {
+            const int item = tile + __builtin_ctzll(todo);
+            const int g = find_graph(starts, nG, item);
+            const GDev &d = G[g];
+            const int v = item - starts[g];
+            const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
+            const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
+            const int k = kout + kin;
+            const int r = d.boff + d.lab[v];
+            const int rb0 = bm.rptr[r], rb1 = bm.rptr[r + 1], cb0 = bm.cptr[r], cb1 = bm.cptr[r + 1];
+            // edge-end keys 2 t + (1 for an in-end), in canonical end order
+            int key_c[4];
+            int ell = 0;
+    #pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = 64 * c + lane;
+                int key = KEY_PAD;
+                if (j < k) {
+                    const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
+                    if (u == v) {
+                        key = KEY_SELF;
+                        if (j < kout) ++ell;
+                    } else {
+                        key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
+                    }
+                }
+                key_c[c] = key;
+            }
+            // proposal: the drawn end's block comes from the lane holding its key
+            const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
+            const double lnu = log(draw_unit(W.w[3]));
+            int s;
+            {
+                const long long eC = (long long)d.eps * d.C;
+                if (k == 0) {
+                    s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+                } else {
+                    const int j = __builtin_amdgcn_readfirstlane((int)draw_idx(W.w[0], (uint64_t)k));
+                    const int c = j >> 6;
+                    const int kc = c == 0 ? key_c[0] : c == 1 ? key_c[1] : c == 2 ? key_c[2] : key_c[3];
+                    const int kj = __builtin_amdgcn_readlane(kc, j & 63);
+                    const int t = kj == KEY_SELF ? r : kj >> 1;
+                    const long long dt = (long long)bm.dout[t] + bm.din[t];
+                    if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+                    else s = s_draw_wave(bm, t, draw_idx(W.w[2], (uint64_t)dt));
+                }
+            }
+            if (s == r) {
+                MoveOut o;
+                o.s = s;
+                if (lane == 0) record_move(d, v, r, o, true, nb, tr);
+                continue;
+            }
+            // rows r, s and columns r, s of M; the short ones staged in LDS
+            MoveLists ML;
+            {
+                const int b0[4] = {rb0, bm.rptr[s], cb0, bm.cptr[s]};
+                const int b1[4] = {rb1, bm.rptr[s + 1], cb1, bm.cptr[s + 1]};
+    #pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int n = b1[l] - b0[l];
+                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + b0[l];
+                    ML.n[l] = n;
+                    if (n <= LEAF_ROW) {
+                        int *sc = SC[wv] + l * LEAF_ROW, *sv = SV[wv] + l * LEAF_ROW;
+                        for (int j = lane; j < n; j += 64) {
+                            sc[j] = gc[j];
+                            sv[j] = gv[j];
+                        }
+                        ML.c[l] = sc;
+                        ML.v[l] = sv;
+                    } else {
+                        ML.c[l] = gc;
+                        ML.v[l] = gv;
+                    }
+                }
+            }
+            const int dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+            ell = wave_sum_i32(ell);
+            // sort: bitonic in registers up to 64 keys, else in LDS
+            int m = 2;
+            while (m < k) m <<= 1;
+            if (k <= 64) {
+                int key = key_c[0];
+                for (int size = 2; size <= m; size <<= 1)
+                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                        const int o = __shfl_xor(key, stride, 64);
+                        key = (((lane & size) == 0) == ((lane & stride) == 0)) ? min(key, o) : max(key, o);
+                    }
+                Kw[lane] = key;
+                wave_sync_lds();
+            } else {
+    #pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (64 * c + lane < m) Kw[64 * c + lane] = key_c[c];
+                wave_sync_lds();
+                for (int size = 2; size <= m; size <<= 1) {
+                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                        for (int q = lane; q < (m >> 1); q += 64) {
+                            const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
+                            const bool asc = (i & size) == 0;
+                            const int a = Kw[i], b = Kw[j];
+                            if ((a > b) == asc) {
+                                Kw[i] = b;
+                                Kw[j] = a;
+                            }
+                        }
+                        wave_sync_lds();
+                    }
+                }
+            }
+            // runs of equal blocks: each run start records its block, its position
+            // and the out-ends before it, so a run's counts are differences of
+            // consecutive starts; the end of the block keys closes the last run
+            const int kk = k - 2 * ell;
+            uint64_t hr = 0, hs = 0;
+            int D = 0, E = 0;
+    #pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int p = 64 * c + lane;
+                const int key = p < kk ? Kw[p] : KEY_PAD;
+                const int prev = (p > 0 && p < kk) ? Kw[p - 1] : -2;
+                const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
+                const uint64_t sm = __ballot(st), em = __ballot(p < kk && !(key & 1));
+                hr |= __ballot(st && (key >> 1) == r);
+                hs |= __ballot(st && (key >> 1) == s);
+                if (st) {
+                    const int idx = D + __popcll(sm & below);
+                    Dt[wv][idx] = key >> 1;
+                    PE[wv][idx] = p | (E + __popcll(em & below)) << 16;
+                }
+                D += __popcll(sm);
+                E += __popcll(em);
+            }
+            if (lane == 0) PE[wv][D] = kk | (kout - ell) << 16;
+            // r and s join the items when no edge end of v points there
+            const int Dx = D + (hr ? 0 : 1) + (hs ? 0 : 1);
+            wave_sync_lds();
+            // per distinct block t: the four entries, then its terms
+            const double eps = (double)d.eps;
+            const double epsC = (double)d.eps * (double)d.C;
+            const int nmax = max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3]));
+            double dL = 0.0, qf = 0.0, qr = 0.0;
+            for (int i = lane; i < Dx; i += 64) {
+                int t, ko = 0, ki = 0;
+                if (i < D) {
+                    const int a0 = PE[wv][i], a1 = PE[wv][i + 1];
+                    t = Dt[wv][i];
+                    ko = (a1 >> 16) - (a0 >> 16);
+                    ki = ((a1 & 0xffff) - (a0 & 0xffff)) - ko;
+                } else {
+                    t = (i == D && !hr) ? r : s;
+                }
+                const int kp = ko | ki << 16;
+                const long long dtt = (long long)bm.dout[t] + bm.din[t];
+                int Mv[4];
+                lists_lookup(ML, nmax, t, Mv);
+                if (t == r) {
+                    CV[wv][0] = Mv[0];  // M_rr
+                    CV[wv][1] = Mv[1];  // M_sr
+                    CV[wv][2] = Mv[3];  // M_rs
+                    CV[wv][3] = kp;
+                } else if (t == s) {
+                    CV[wv][4] = Mv[1];  // M_ss
+                    CV[wv][5] = kp;
+                } else {
+                    block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+                }
+            }
+            wave_sync_lds();
+            {
+                const CornerIn c{CV[wv][0], CV[wv][2], CV[wv][1], CV[wv][4], CV[wv][3], CV[wv][5], ell, kout, kin,
+                                 dor, dos, dir, dis};
+                corner_term(lane, c, eps, epsC, dL, qf, qr);
+            }
+            dL = wave_sum(dL);
+            qf = wave_sum(qf);
+            qr = wave_sum(qr);
             MoveOut o;
             o.s = s;
-            if (lane == 0) record_move(d, v, r, o, true, nb, tr);
-            continue;
+            o.dS = -dL;
+            o.lnH = k > 0 ? log(qr) - log(qf) : 0.0;
+            const double z = -d.beta * o.dS + o.lnH;
+            o.margin = z - lnu;
+            o.accept = lnu < z;
+            if (lane == 0) record_move(d, v, r, o, false, nb, tr);
+            wave_sync_lds();
         }
-        // rows r, s and columns r, s of M, loaded while the keys are built
-        MoveLists ML;
-        ML.sc = SC[wv];
-        ML.sv = SV[wv];
-        {
-            const int rs[4] = {r, s, r, s};
+    }
+}
+
+constexpr int SMALL_WAVES = 4;
+constexpr int SMALL_ROW = 32;  // list entries staged per 16-lane group
+
+// Sum over an aligned group of 16 lanes (a DPP row): pairs, quads, the
+// mirrored half, then the mirrored row.  Each step adds the same two values on
+// every lane (in either order), so the whole row ends with one identical sum.
+__device__ __forceinline__ double grp16_sum(double x) {
+    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141>(x);  // row_half_mirror
+    x += dpp_f64<0x140>(x);  // row_mirror
+    return x;
+}
+__device__ __forceinline__ int grp16_sum_i32(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
+    return x;
+}
+
+// Four vertices with at most SMALL_K edge ends per wave, a 16-lane group each
+// with one edge end per lane: the steps of the wave kernel with group-wide
+// ballots, a 16-way proposal search run by all drawing groups together, a
+// 16-lane bitonic sort and DPP row sums.  A group left without a vertex in
+// the last round of a tile repeats group 0's and records nothing.
+__global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__restrict__ G,
+                                                                 const int *__restrict__ starts, int nG, int n_items,
+                                                                 SparseBM bm, int *__restrict__ nb, SweepTraceDev tr) {
+    __shared__ int SC[SMALL_WAVES * 4][4 * SMALL_ROW], SV[SMALL_WAVES * 4][4 * SMALL_ROW];
+    __shared__ int Dt[SMALL_WAVES * 4][SMALL_K], PE[SMALL_WAVES * 4][SMALL_K + 1];
+    __shared__ int CV[SMALL_WAVES * 4][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, gi = lane >> 4, gl = lane & 15;
+    const int gs = 4 * wv + gi;  // the group's LDS slot
+    const int sh = 16 * gi;
+    const uint64_t gm = 0xffffull << sh, gbelow = lanemask_lt() & gm;
+    const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * SMALL_WAVES + wv), nw = gridDim.x * SMALL_WAVES;
+    for (int tile = gw * 64; tile < n_items; tile += nw * 64) {
+        uint64_t todo = __ballot(sweep_item(G, starts, nG, n_items, tile + lane, 0, SMALL_K));
+        while (todo) {
+            int pick[4];
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int *ptr = l < 2 ? bm.rptr : bm.cptr;
-                ML.b0[l] = ptr[rs[l]];
-                ML.len[l] = ptr[rs[l] + 1] - ML.b0[l];
+            for (int q = 0; q < 4; ++q) {
+                pick[q] = todo ? __builtin_ctzll(todo) : -1;
+                todo &= todo - 1;
             }
-#pragma unroll
-            for (int l = 0; l < 4; ++l)
-                if (ML.len[l] <= LEAF_ROW) {
-                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + ML.b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + ML.b0[l];
-                    for (int j = lane; j < ML.len[l]; j += 64) {
-                        SC[wv][l * LEAF_ROW + j] = gc[j];
-                        SV[wv][l * LEAF_ROW + j] = gv[j];
-                    }
-                }
-        }
-        // edge-end keys 2 t + dir; self-loop ends and padding sort last
-        int ell = 0;
-        int m = 2;
-        while (m < k) m <<= 1;
-        for (int j = lane; j < m; j += 64) {
-            int key = KEY_PAD;
-            if (j < k) {
-                const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
+            const int mine = gi == 0 ? pick[0] : gi == 1 ? pick[1] : gi == 2 ? pick[2] : pick[3];
+            const bool act = mine >= 0;
+            const int item = tile + (act ? mine : pick[0]);
+            const int g = find_graph(starts, nG, item);
+            const GDev &d = G[g];
+            const int v = item - starts[g];
+            const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
+            const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
+            const int k = kout + kin;
+            const int r = d.boff + d.lab[v];
+            const int rb0 = bm.rptr[r], rb1 = bm.rptr[r + 1], cb0 = bm.cptr[r], cb1 = bm.cptr[r + 1];
+            // the edge end of this lane: key 2 t + (1 for an in-end)
+            int key = KEY_PAD, ell = 0;
+            if (gl < k) {
+                const int u = gl < kout ? d.out_idx[op + gl] : d.in_idx[ip + gl - kout];
                 if (u == v) {
-                    if (j < kout) ++ell;
+                    key = KEY_SELF;
+                    ell = gl < kout ? 1 : 0;
                 } else {
-                    key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
+                    key = 2 * (d.boff + d.lab[u]) + (gl < kout ? 0 : 1);
                 }
             }
-            Kw[j] = key;
-        }
-        ell = wave_sum_i32(ell);
-        wave_sync_lds();
-        for (int size = 2; size <= m; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int q = lane; q < (m >> 1); q += 64) {
-                    const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
-                    const bool asc = (i & size) == 0;
-                    const int a = Kw[i], b = Kw[j];
-                    if ((a > b) == asc) {
-                        Kw[i] = b;
-                        Kw[j] = a;
-                    }
-                }
-                wave_sync_lds();
-            }
-        }
-        // run-length encode into (t, ko, ki) with 4 x 64-bit masks
-        const int kk = k - 2 * ell;
-        uint64_t sm[4], em[4];
-        int key_c[4];
-        bool st_c[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int p = 64 * c + lane;
-            const int key = p < kk ? Kw[p] : KEY_PAD;
-            const int prev = (p > 0 && p < kk) ? Kw[p - 1] : -2;
-            const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
-            sm[c] = __ballot(st);
-            em[c] = __ballot(p < kk && !(key & 1));
-            key_c[c] = key;
-            st_c[c] = st;
-        }
-        int D = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) D += __popcll(sm[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (!st_c[c]) continue;
-            const int p = 64 * c + lane;
-            int idx = 0;
-            for (int c2 = 0; c2 < c; ++c2) idx += __popcll(sm[c2]);
-            idx += __popcll(sm[c] & below);
-            int end = kk;
-            const uint64_t after = (lane == 63) ? 0ull : (sm[c] & ~((2ull << lane) - 1));
-            if (after) {
-                end = 64 * c + __builtin_ctzll(after);
+            // proposal
+            const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
+            const double lnu = log(draw_unit(W.w[3]));
+            int s = 0;
+            long long x = -1;  // draw into t's running sums, or -1
+            int t = r;
+            if (k == 0) {
+                s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
             } else {
-                for (int c2 = c + 1; c2 < 4; ++c2)
-                    if (sm[c2]) {
-                        end = 64 * c2 + __builtin_ctzll(sm[c2]);
-                        break;
-                    }
+                const int kj = __shfl(key, sh + (int)draw_idx(W.w[0], (uint64_t)k), 64);
+                t = kj == KEY_SELF ? r : kj >> 1;
+                const long long eC = (long long)d.eps * d.C;
+                const long long dt = (long long)bm.dout[t] + bm.din[t];
+                if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+                else x = draw_idx(W.w[2], (uint64_t)dt);
             }
-            auto evens_below = [&](int x) {
-                int e = 0;
-                for (int c2 = 0; c2 < 4; ++c2) {
-                    if (64 * (c2 + 1) <= x) e += __popcll(em[c2]);
-                    else {
-                        if (x > 64 * c2) e += __popcll(em[c2] & (~0ull >> (64 - (x - 64 * c2))));
-                        break;
+            {
+                int lo = 0, hi = 1;
+                if (x >= 0) {
+                    lo = bm.rptr[t] + bm.cptr[t];
+                    hi = bm.rptr[t + 1] + bm.cptr[t + 1];
+                }
+                while (__ballot(hi - lo > 1)) {
+                    const bool more = hi - lo > 1;
+                    const int st = (hi - lo + 15) >> 4;
+                    const int p = min(lo + (gl + 1) * st, hi) - 1;  // the last probe is hi - 1, whose sum exceeds x
+                    const bool above = more && (long long)bm.scum[p] > x;
+                    const int f = __builtin_ctzll((__ballot(above) & gm) >> sh | 0x10000ull);
+                    if (more) {
+                        const int nlo = min(lo + f * st, hi);
+                        hi = min(lo + (f + 1) * st, hi);
+                        lo = nlo;
                     }
                 }
-                return e;
-            };
-            const int ko = evens_below(end) - evens_below(p);
-            Dt[wv][idx] = key_c[c] >> 1;
-            Dko[wv][idx] = ko;
-            Dki[wv][idx] = (end - p) - ko;
+                if (x >= 0) s = bm.scol[lo];
+            }
+            const bool live = act && s != r;
+            if (act && !live && gl == 0) {
+                MoveOut o;
+                o.s = s;
+                record_move(d, v, r, o, true, nb, tr);
+            }
+            // rows r, s and columns r, s of M; the short ones staged in LDS
+            MoveLists ML;
+            {
+                const int b0[4] = {rb0, bm.rptr[s], cb0, bm.cptr[s]};
+                const int b1[4] = {rb1, bm.rptr[s + 1], cb1, bm.cptr[s + 1]};
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int n = b1[l] - b0[l];
+                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + b0[l];
+                    ML.n[l] = n;
+                    if (n <= SMALL_ROW) {
+                        int *sc = SC[gs] + l * SMALL_ROW, *sv = SV[gs] + l * SMALL_ROW;
+                        for (int j = gl; j < n; j += 16) {
+                            sc[j] = gc[j];
+                            sv[j] = gv[j];
+                        }
+                        ML.c[l] = sc;
+                        ML.v[l] = sv;
+                    } else {
+                        ML.c[l] = gc;
+                        ML.v[l] = gv;
+                    }
+                }
+            }
+            const int dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+            ell = grp16_sum_i32(ell);
+            // 16-lane bitonic sort of the group's keys
+#pragma unroll
+            for (int size = 2; size <= 16; size <<= 1)
+#pragma unroll
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    const int o = __shfl_xor(key, stride, 64);
+                    key = (((gl & size) == 0) == ((gl & stride) == 0)) ? min(key, o) : max(key, o);
+                }
+            // runs of equal blocks, recorded as in the wave kernel
+            const int kk = k - 2 * ell;
+            const int prev = __shfl_up(key, 1, 16);
+            const bool st = gl < kk && (gl == 0 || (key >> 1) != (prev >> 1));
+            const uint64_t sm = __ballot(st) & gm, em = __ballot(gl < kk && !(key & 1)) & gm;
+            const bool hr = (__ballot(st && (key >> 1) == r) & gm) != 0;
+            const bool hs = (__ballot(st && (key >> 1) == s) & gm) != 0;
+            const int D = __popcll(sm);
+            if (st) {
+                const int idx = __popcll(sm & gbelow);
+                Dt[gs][idx] = key >> 1;
+                PE[gs][idx] = gl | __popcll(em & gbelow) << 16;
+            }
+            if (gl == 0) PE[gs][D] = kk | (kout - ell) << 16;
+            const int Dx = D + (hr ? 0 : 1) + (hs ? 0 : 1);
+            wave_sync_lds();
+            const double eps = (double)d.eps;
+            const double epsC = (double)d.eps * (double)d.C;
+            const int nmax = max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3]));
+            double dL = 0.0, qf = 0.0, qr = 0.0;
+            for (int i = gl; i < Dx; i += 16) {
+                int tt, ko = 0, ki = 0;
+                if (i < D) {
+                    const int a0 = PE[gs][i], a1 = PE[gs][i + 1];
+                    tt = Dt[gs][i];
+                    ko = (a1 >> 16) - (a0 >> 16);
+                    ki = ((a1 & 0xffff) - (a0 & 0xffff)) - ko;
+                } else {
+                    tt = (i == D && !hr) ? r : s;
+                }
+                const long long dtt = (long long)bm.dout[tt] + bm.din[tt];
+                int Mv[4];
+                lists_lookup(ML, nmax, tt, Mv);
+                if (tt == r) {
+                    CV[gs][0] = Mv[0];  // M_rr
+                    CV[gs][1] = Mv[1];  // M_sr
+                    CV[gs][2] = Mv[3];  // M_rs
+                    CV[gs][3] = ko | ki << 16;
+                } else if (tt == s) {
+                    CV[gs][4] = Mv[1];  // M_ss
+                    CV[gs][5] = ko | ki << 16;
+                } else {
+                    block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+                }
+            }
+            wave_sync_lds();
+            {
+                const CornerIn c{CV[gs][0], CV[gs][2], CV[gs][1], CV[gs][4], CV[gs][3], CV[gs][5], ell, kout, kin,
+                                 dor, dos, dir, dis};
+                corner_term(gl, c, eps, epsC, dL, qf, qr);
+            }
+            dL = grp16_sum(dL);
+            qf = grp16_sum(qf);
+            qr = grp16_sum(qr);
+            MoveOut o;
+            o.s = s;
+            o.dS = -dL;
+            o.lnH = k > 0 ? log(qr) - log(qf) : 0.0;
+            const double z = -d.beta * o.dS + o.lnH;
+            o.margin = z - lnu;
+            o.accept = lnu < z;
+            if (live && gl == 0) record_move(d, v, r, o, false, nb, tr);
+            wave_sync_lds();
         }
-        wave_sync_lds();
-        const MoveOut o = move_terms_lists(d, bm, ML, r, s, Dt[wv], Dko[wv], Dki[wv], D, ell, kout, kin, lnu);
-        if (lane == 0) record_move(d, v, r, o, false, nb, tr);
-        wave_sync_lds();
     }
 }
 
@@ -584,105 +845,29 @@ constexpr int HUB_THREADS = 512;
 constexpr size_t HUB_SLOT_INTS = 4 * (size_t)SBP_MAX_DEGREE_DEV;
 constexpr int HUB_LDS = 8192;  // hubs with at most this many sort keys work in LDS
 
-// The move terms of a hub from its distinct neighbour blocks (dt, packed
-// counts dk = out | in << 16), every thread of the workgroup taking items;
-// partial sums are reduced per wave and then in wave order, so the result
-// does not depend on timing.
-__device__ __forceinline__ MoveOut move_terms_block(const GDev &d, const SparseBM &bm, int r, int s, const int *dt,
-                                                    const int *dk, int D, int ell, int kout, int kin, double lnu,
-                                                    double *red_d, int *red_i) {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double eps = (double)d.eps;
-    const double epsC = (double)d.eps * (double)d.C;
-    double dL = 0.0, qf = 0.0, qr = 0.0;
-    int ko_r = 0, ki_r = 0, ko_s = 0, ki_s = 0;
-    for (int i = tid; i < D; i += HUB_THREADS) {
-        const int t = dt[i], ko = dk[i] & 0xffff, ki = dk[i] >> 16;
-        if (t == r) {
-            ko_r = ko;
-            ki_r = ki;
-            continue;
-        }
-        if (t == s) {
-            ko_s = ko;
-            ki_s = ki;
-            continue;
-        }
-        const int Mrt = m_get(bm, r, t), Mst = m_get(bm, s, t);
-        const int Mtr = m_get(bm, t, r), Mts = m_get(bm, t, s);
-        if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
-        if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
-        const double kt = (double)(ko + ki);
-        const double den = (double)((long long)bm.dout[t] + bm.din[t]) + epsC;
-        qf += kt * (((double)(Mts + Mst) + eps) / den);
-        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
-    }
-    dL = wave_sum(dL);
-    qf = wave_sum(qf);
-    qr = wave_sum(qr);
-    ko_r = wave_sum_i32(ko_r);
-    ki_r = wave_sum_i32(ki_r);
-    ko_s = wave_sum_i32(ko_s);
-    ki_s = wave_sum_i32(ki_s);
-    if (lane == 0) {
-        red_d[3 * wv + 0] = dL;
-        red_d[3 * wv + 1] = qf;
-        red_d[3 * wv + 2] = qr;
-        red_i[4 * wv + 0] = ko_r;
-        red_i[4 * wv + 1] = ki_r;
-        red_i[4 * wv + 2] = ko_s;
-        red_i[4 * wv + 3] = ki_s;
-    }
-    __syncthreads();
-    MoveOut o;
-    o.s = s;
-    if (tid == 0) {
-        dL = qf = qr = 0.0;
-        ko_r = ki_r = ko_s = ki_s = 0;
-        for (int w = 0; w < HUB_THREADS / 64; ++w) {
-            dL += red_d[3 * w + 0];
-            qf += red_d[3 * w + 1];
-            qr += red_d[3 * w + 2];
-            ko_r += red_i[4 * w + 0];
-            ki_r += red_i[4 * w + 1];
-            ko_s += red_i[4 * w + 2];
-            ki_s += red_i[4 * w + 3];
-        }
-        const int Mrr = m_get(bm, r, r), Mrs = m_get(bm, r, s), Msr = m_get(bm, s, r), Mss = m_get(bm, s, s);
-        const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
-        dL += xlogx((double)(Mrr + drr)) - xlogx((double)Mrr);
-        dL += xlogx((double)(Mrs + drs)) - xlogx((double)Mrs);
-        dL += xlogx((double)(Msr + dsr)) - xlogx((double)Msr);
-        dL += xlogx((double)(Mss + dss)) - xlogx((double)Mss);
-        const double dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
-        dL -= xlogx(dor - kout) - xlogx(dor) + xlogx(dos + kout) - xlogx(dos);
-        dL -= xlogx(dir - kin) - xlogx(dir) + xlogx(dis + kin) - xlogx(dis);
-        const double k = (double)(kout + kin);
-        const double d_r = dor + dir, d_s = dos + dis;
-        const int kr = ko_r + ki_r + 2 * ell, ks = ko_s + ki_s;
-        if (kr) qf += (double)kr * (((double)(Mrs + Msr) + eps) / (d_r + epsC));
-        if (ks) qf += (double)ks * (((double)(2 * Mss) + eps) / (d_s + epsC));
-        const int kr2 = ko_r + ki_r, ks2 = ko_s + ki_s + 2 * ell;
-        if (kr2) qr += (double)kr2 * (((double)(2 * (Mrr + drr)) + eps) / (d_r - k + epsC));
-        if (ks2) qr += (double)ks2 * (((double)(Msr + dsr + Mrs + drs) + eps) / (d_s + k + epsC));
-        o.dS = -dL;
-        o.lnH = (kout + kin) > 0 ? log(qr) - log(qf) : 0.0;
-        const double z = -d.beta * o.dS + o.lnH;
-        o.margin = z - lnu;
-        o.accept = lnu < z;
-    }
-    return o;
-}
+// Per-workgroup LDS of the hub kernel besides the sort and item arrays.
+struct HubShared {
+    double red_d[3 * (HUB_THREADS / 64)];
+    int cnt_s[HUB_THREADS / 64], cnt_e[HUB_THREADS / 64], flg[HUB_THREADS / 64];
+    int red[HUB_THREADS / 64];
+    int cv[6];  // M_rr, M_sr, M_rs, M_ss, then v's packed out | in << 16 ends into r and s
+};
 
-// One hub: its sort keys (2 * neighbour block + in-end flag, self-loop ends
-// padded out) sorted by a bitonic network in K, the runs of equal block by
-// wave 0 into (Dt, Dk), then the move terms.  K, Dt, Dk hold m, kk, kk ints;
-// with the LDS arrays the whole hub stays on the CU.
+// One hub v moving r -> s.  K (kcap ints) first holds the sort keys
+// (2 * neighbour block + in-end flag; self-loop ends and padding after them),
+// sorted by a bitonic network; the workgroup then records the runs of equal
+// block (block in Dt, start position and out-ends before it in PE) and reuses
+// K for the M entries of the items: each entry of row r, row s, column r and
+// column s finds its index among the sorted items by a binary search and
+// stores its value there (as many lists as K has room for; the rest are
+// searched per item), catching the corner entries on the way.  Partial sums
+// are reduced per wave and then in wave order, so the result does not depend
+// on timing.
 __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int v, int r, int s, int op, int kout,
-                                         int ip, int kin, int m, double lnu, int *K, int *Dt, int *Dk, int *nb,
-                                         const SweepTraceDev &tr, int *red, int *s_ell, int *s_D, double *red_d,
-                                         int *red_i) {
+                                         int ip, int kin, int m, int kcap, double lnu, int *K, int *Dt, int *PE,
+                                         int *nb, const SweepTraceDev &tr, HubShared &H) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint64_t below = lanemask_lt();
     const int k = kout + kin;
     int ell = 0;
     for (int j = tid; j < m; j += HUB_THREADS) {
@@ -690,6 +875,7 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
         if (j < k) {
             const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + j - kout];
             if (u == v) {
+                key = KEY_SELF;
                 if (j < kout) ++ell;
             } else {
                 key = 2 * (d.boff + d.lab[u]) + (j < kout ? 0 : 1);
@@ -698,15 +884,11 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
         K[j] = key;
     }
     ell = wave_sum_i32(ell);
-    if (lane == 0) red[wv] = ell;
-    __syncthreads();
-    if (tid == 0) {
-        int t = 0;
-        for (int w = 0; w < HUB_THREADS / 64; ++w) t += red[w];
-        *s_ell = t;
-    }
+    if (lane == 0) H.red[wv] = ell;
+    if (tid < 6) H.cv[tid] = 0;
     for (int size = 2; size <= m; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
             for (int q = tid; q < (m >> 1); q += HUB_THREADS) {
                 const int i = 2 * stride * (q / stride) + (q % stride), j = i + stride;
                 const bool asc = (i & size) == 0;
@@ -716,67 +898,162 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
                     K[j] = a;
                 }
             }
-            __threadfence_block();
-            __syncthreads();
         }
     }
-    ell = *s_ell;
-    const int kk = k - 2 * ell;
-    // run starts, in order, by wave 0 scanning 64 positions at a time
-    if (wv == 0) {
-        int D = 0;
-        int pend_idx = -1, pend_p = 0, pend_key = 0, evens = 0, pend_evens = 0;
-        for (int base = 0; base < kk; base += 64) {
-            const int p = base + lane;
-            const int key = p < kk ? K[p] : KEY_PAD;
-            const int prev = (p > 0 && p < kk) ? K[p - 1] : -2;
-            const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
-            const bool ev = p < kk && !(key & 1);
-            const uint64_t sm = __ballot(st), em = __ballot(ev);
-            // close runs: every start in this chunk ends the previous run
-            uint64_t rest = sm;
-            while (rest) {
-                const int b = __builtin_ctzll(rest);
-                rest &= rest - 1;
-                const int pos = base + b;
-                const int ev_before = evens + __popcll(em & ((b ? (~0ull >> (64 - b)) : 0ull)));
-                if (pend_idx >= 0 && lane == 0) {
-                    const int ko = ev_before - pend_evens;
-                    Dt[pend_idx] = pend_key >> 1;
-                    Dk[pend_idx] = ko | (((pos - pend_p) - ko) << 16);
-                }
-                pend_idx = D++;
-                pend_p = pos;
-                pend_key = __shfl(key, b, SBP_WAVE);
-                pend_evens = ev_before;
-            }
-            evens += __popcll(em);
-        }
-        if (pend_idx >= 0 && lane == 0) {
-            const int ko = evens - pend_evens;
-            Dt[pend_idx] = pend_key >> 1;
-            Dk[pend_idx] = ko | (((kk - pend_p) - ko) << 16);
-        }
-        if (lane == 0) *s_D = D;
-    }
-    __threadfence_block();
     __syncthreads();
-    const MoveOut o = move_terms_block(d, bm, r, s, Dt, Dk, *s_D, ell, kout, kin, lnu, red_d, red_i);
-    if (tid == 0) record_move(d, v, r, o, false, nb, tr);
+    ell = 0;
+    for (int w = 0; w < HUB_THREADS / 64; ++w) ell += H.red[w];
+    const int kk = k - 2 * ell;
+    // runs, HUB_THREADS positions at a time
+    int D = 0, E = 0, fl = 0;
+    for (int base = 0; base < kk; base += HUB_THREADS) {
+        const int p = base + tid;
+        const int key = p < kk ? K[p] : KEY_PAD;
+        const int prev = (p > 0 && p < kk) ? K[p - 1] : -2;
+        const bool st = p < kk && (p == 0 || (key >> 1) != (prev >> 1));
+        const uint64_t sm = __ballot(st), em = __ballot(p < kk && !(key & 1));
+        const bool fr = __ballot(st && (key >> 1) == r) != 0, fs = __ballot(st && (key >> 1) == s) != 0;
+        if (lane == 0) {
+            H.cnt_s[wv] = __popcll(sm);
+            H.cnt_e[wv] = __popcll(em);
+            H.flg[wv] = (fr ? 1 : 0) | (fs ? 2 : 0);
+        }
+        __syncthreads();
+        int ps = D, pe = E;
+        for (int w = 0; w < HUB_THREADS / 64; ++w) {
+            if (w < wv) {
+                ps += H.cnt_s[w];
+                pe += H.cnt_e[w];
+            }
+            D += H.cnt_s[w];
+            E += H.cnt_e[w];
+            fl |= H.flg[w];
+        }
+        if (st) {
+            const int idx = ps + __popcll(sm & below);
+            Dt[idx] = key >> 1;
+            PE[idx] = p | (pe + __popcll(em & below)) << 16;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) PE[D] = kk | (kout - ell) << 16;
+    const bool hr = (fl & 1) != 0, hs = (fl & 2) != 0;
+    const int Dx = D + (hr ? 0 : 1) + (hs ? 0 : 1);
+    // M entries of the items: the lists that fit in K are joined, the others searched
+    MoveLists ML;
+    {
+        const int b0[4] = {bm.rptr[r], bm.rptr[s], bm.cptr[r], bm.cptr[s]};
+        const int b1[4] = {bm.rptr[r + 1], bm.rptr[s + 1], bm.cptr[r + 1], bm.cptr[s + 1]};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            ML.c[l] = (l < 2 ? bm.rcol : bm.crow) + b0[l];
+            ML.v[l] = (l < 2 ? bm.rval : bm.cval) + b0[l];
+            ML.n[l] = b1[l] - b0[l];
+        }
+    }
+    const int nA = min(4, kcap / max(D, 1));
+    for (int i = tid; i < nA * D; i += HUB_THREADS) K[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        if (l >= nA) break;
+        for (int j = tid; j < ML.n[l]; j += HUB_THREADS) {
+            const int c = ML.c[l][j], val = ML.v[l][j];
+            int lo = 0;
+            for (int st = D > 0 ? 1 << (31 - __clz(D)) : 0; st > 0; st >>= 1)
+                if (lo + st <= D && Dt[lo + st - 1] < c) lo += st;
+            if (lo < D && Dt[lo] == c) K[l * D + lo] = val;
+            if (l < 2) {
+                if (c == r) H.cv[l] = val;      // M_rr from row r, M_sr from row s
+                if (c == s) H.cv[2 + l] = val;  // M_rs from row r, M_ss from row s
+            }
+        }
+    }
+    MoveLists MS = ML;  // the lists left to search
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        if (l < nA) MS.n[l] = 0;
+    const int nmax = max(max(MS.n[0], MS.n[1]), max(MS.n[2], MS.n[3]));
+    __syncthreads();
+    const double eps = (double)d.eps;
+    const double epsC = (double)d.eps * (double)d.C;
+    double dL = 0.0, qf = 0.0, qr = 0.0;
+    for (int i = tid; i < Dx; i += HUB_THREADS) {
+        int t, ko = 0, ki = 0;
+        if (i < D) {
+            const int a0 = PE[i], a1 = PE[i + 1];
+            t = Dt[i];
+            ko = (a1 >> 16) - (a0 >> 16);
+            ki = ((a1 & 0xffff) - (a0 & 0xffff)) - ko;
+        } else {
+            t = (i == D && !hr) ? r : s;
+        }
+        const bool corner = t == r || t == s;
+        if (corner) H.cv[t == r ? 4 : 5] = ko | ki << 16;
+        if (corner && nA >= 2) continue;  // the corner entries came with the joins
+        int Mv[4];
+        if (corner) {
+            MoveLists MA = ML;
+            lists_lookup(MA, max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3])), t, Mv);
+            if (t == r) {
+                H.cv[0] = Mv[0];
+                H.cv[1] = Mv[1];
+            } else {
+                H.cv[2] = Mv[0];
+                H.cv[3] = Mv[1];
+            }
+            continue;
+        }
+        const long long dtt = (long long)bm.dout[t] + bm.din[t];
+        lists_lookup(MS, nmax, t, Mv);
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            if (l < nA) Mv[l] = K[l * D + i];
+        block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+    }
+    __syncthreads();
+    if (tid < 12) {
+        const CornerIn c{H.cv[0], H.cv[2], H.cv[1], H.cv[3], H.cv[4], H.cv[5], ell, kout, kin,
+                         bm.dout[r], bm.dout[s], bm.din[r], bm.din[s]};
+        corner_term(tid, c, eps, epsC, dL, qf, qr);
+    }
+    dL = wave_sum(dL);
+    qf = wave_sum(qf);
+    qr = wave_sum(qr);
+    if (lane == 0) {
+        H.red_d[3 * wv + 0] = dL;
+        H.red_d[3 * wv + 1] = qf;
+        H.red_d[3 * wv + 2] = qr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        dL = qf = qr = 0.0;
+        for (int w = 0; w < HUB_THREADS / 64; ++w) {
+            dL += H.red_d[3 * w + 0];
+            qf += H.red_d[3 * w + 1];
+            qr += H.red_d[3 * w + 2];
+        }
+        MoveOut o;
+        o.s = s;
+        o.dS = -dL;
+        o.lnH = k > 0 ? log(qr) - log(qf) : 0.0;
+        const double z = -d.beta * o.dS + o.lnH;
+        o.margin = z - lnu;
+        o.accept = lnu < z;
+        record_move(d, v, r, o, false, nb, tr);
+    }
 }
 
 // Sweep evaluation of hub vertices (more than SBP_LEAF_MAX edge ends): a
-// workgroup per hub.
+// workgroup per hub, in LDS up to HUB_LDS sort keys, else in its global slot.
 __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restrict__ G, const int *__restrict__ starts,
                                                            int nG, int n_items, SparseBM bm, int *__restrict__ nb,
                                                            SweepTraceDev tr, int *__restrict__ scratch) {
-    __shared__ int Ks[HUB_LDS], Dts[HUB_LDS], Dks[HUB_LDS];
-    __shared__ int red[HUB_THREADS / 64], red_i[4 * (HUB_THREADS / 64)];
-    __shared__ double red_d[3 * (HUB_THREADS / 64)];
-    __shared__ int s_ell, s_D;
+    __shared__ int Ks[HUB_LDS], Dts[HUB_LDS], PEs[HUB_LDS + 1];
+    __shared__ HubShared H;
     int *Kg = scratch + (size_t)blockIdx.x * HUB_SLOT_INTS;
     int *Dtg = Kg + SBP_MAX_DEGREE_DEV;
-    int *Dkg = Dtg + SBP_MAX_DEGREE_DEV;
+    int *PEg = Dtg + SBP_MAX_DEGREE_DEV;
     const int tid = threadIdx.x;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int g = find_graph(starts, nG, item);
@@ -793,22 +1070,30 @@ __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restric
         }
         const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
         const double lnu = log(draw_unit(W.w[3]));
-        const int s = propose(d, bm, v, r, kout, kin, W);
+        int s;
+        {
+            const long long eC = (long long)d.eps * d.C;
+            const int j = (int)draw_idx(W.w[0], (uint64_t)k);
+            const int u = j < kout ? d.out_idx[op + j] : d.in_idx[ip + (j - kout)];
+            const int t = d.boff + d.lab[u];
+            const long long dt = (long long)bm.dout[t] + bm.din[t];
+            if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+            else s = s_draw_wave(bm, t, draw_idx(W.w[2], (uint64_t)dt));
+        }
         if (s == r) {
             if (tid == 0) {
                 MoveOut o;
                 o.s = s;
                 record_move(d, v, r, o, true, nb, tr);
             }
-            __syncthreads();
             continue;
         }
         int m = 2;
         while (m < k) m <<= 1;
         if (m <= HUB_LDS)
-            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, lnu, Ks, Dts, Dks, nb, tr, red, &s_ell, &s_D, red_d, red_i);
+            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, HUB_LDS, lnu, Ks, Dts, PEs, nb, tr, H);
         else
-            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, lnu, Kg, Dtg, Dkg, nb, tr, red, &s_ell, &s_D, red_d, red_i);
+            hub_move(d, bm, v, r, s, op, kout, ip, kin, m, SBP_MAX_DEGREE_DEV, lnu, Kg, Dtg, PEg, nb, tr, H);
         __syncthreads();
     }
 }
@@ -1216,7 +1501,7 @@ int build_union_sparse(const GDev *dG, const StepMeta &m, SparseBM &bm, UnionScr
     bm.Ctot = Ctot;
     int rc;
     // 1. one key per edge: (block of source) * Ctot + block of target, sorted
-    hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G, (int)m.Ntot,
+    hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(m.Ntot, BLK, 16384)), dim3(BLK), 0, s, dG, m.voff, m.G, (int)m.Ntot,
                        Ctot, ws.k0);
     SBP_LAUNCH_CHECK();
     if ((rc = radix_sort(ws.k0, ws.k1, nullptr, nullptr, Etot, ceil_log2((uint64_t)Ctot * (uint64_t)Ctot), ws.temp, s)))
@@ -1264,7 +1549,10 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     {
     ProfileScope prof("sweep_eval", s);
     if (m.n_leaf > 0) {
-        hipLaunchKernelGGL(k_sweep_leaf, dim3(grid_for(m.n_leaf, LEAF_WAVES, 16384)), dim3(LEAF_WAVES * 64), 0, s, dG,
+        const long long tiles = ((long long)m.n_leaf + 63) / 64;
+        hipLaunchKernelGGL(k_sweep_small, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0, s, dG,
+                           m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
+        hipLaunchKernelGGL(k_sweep_leaf, dim3(grid_for(tiles, LEAF_WAVES, 16384)), dim3(LEAF_WAVES * 64), 0, s, dG,
                            m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         SBP_LAUNCH_CHECK();
     }

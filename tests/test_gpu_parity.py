@@ -192,6 +192,31 @@ def test_sweep_200k_sparse_tier():
     sweep_parity(g, lab0, 500, seed=17, sweep=0)
 
 
+def hub_graph():
+    """24k vertices with five hubs of 500 to 15000 edge ends over a sparse
+    random background: against thousands of blocks their distinct neighbour
+    blocks fill all four, some or only one of the joined lists, in LDS and in
+    the global slot."""
+    rng = np.random.default_rng(77)
+    n = 24000
+    src, dst = [], []
+    for h, (ko, ki) in enumerate([(300, 200), (1500, 1400), (2600, 2000), (4200, 3000), (9000, 6000)]):
+        src += [h] * ko + list(rng.integers(0, n, ki))
+        dst += list(rng.integers(0, n, ko)) + [h] * ki
+    src += list(rng.integers(0, n, 60000))
+    dst += list(rng.integers(0, n, 60000))
+    return gen.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("C", [20000, 9000, 600])
+def test_sweep_hubs_many_blocks(C):
+    g = hub_graph()
+    dg = sbp.DeviceGraph(g)
+    lab0 = gen.initial_labels(g.n, C, seed=C)
+    for sweep in range(3):
+        sweep_parity(g, lab0, C, seed=41, sweep=sweep, dg=dg)
+
+
 # ---------------------------------------------------------------- merges
 def merge_parity(g, lab0, C, seed, phase, x=10, eps=1):
     dg = sbp.DeviceGraph(g)
