@@ -302,7 +302,7 @@ constexpr int LEAF_WAVES = 4;
 constexpr int KEY_PAD = 0x7fffffff;
 constexpr int KEY_SELF = 0x7ffffffe;  // self-loop end: after every block key, before the padding
 
-constexpr int SMALL_K = 16;  // vertices with at most this many edge ends go four to a wave
+constexpr int SMALL_K = 16;  // vertices with at most this many edge ends go four or eight to a wave
 
 // Whether flat sweep item i is a vertex of the current batch with kmin..kmax
 // edge ends.
@@ -316,20 +316,22 @@ __device__ __forceinline__ bool sweep_item(const GDev *G, const int *starts, int
     return (v % d.n_batches) == d.batch && k >= kmin && k <= kmax;
 }
 
-// s_draw by a whole wave: each round probes 64 evenly spaced running sums and
-// keeps the stretch between the last probe at or below x and the first above.
-__device__ __forceinline__ int s_draw_wave(const SparseBM &bm, int t, long long x) {
+// s_draw by a whole wave over t's running sums [lo, hi): each round probes 64
+// evenly spaced sums and keeps the stretch between the last probe at or below
+// x and the first above; the probes read their blocks too, so the round that
+// probes single entries yields s.
+__device__ __forceinline__ int s_draw_wave(const SparseBM &bm, int lo, int hi, long long x) {
     const int lane = threadIdx.x & 63;
-    int lo = bm.rptr[t] + bm.cptr[t], hi = bm.rptr[t + 1] + bm.cptr[t + 1];  // answer in [lo, hi)
-    while (hi - lo > 1) {
+    for (;;) {
         const int st = (hi - lo + 63) >> 6;
         const int p = min(lo + (lane + 1) * st, hi) - 1;  // the last probe is hi - 1, whose sum d_t exceeds x
-        const int f = __builtin_ctzll(__ballot((long long)bm.scum[p] > x));
+        const int sc = bm.scum[p], sb = bm.scol[p];
+        const int f = __builtin_ctzll(__ballot((long long)sc > x));
+        if (st == 1) return __shfl(sb, f, 64);
         const int nlo = min(lo + f * st, hi);
         hi = min(lo + (f + 1) * st, hi);
         lo = nlo;
     }
-    return bm.scol[lo];
 }
 
 // Row r, row s, column r and column s of M for one move: list l holds
@@ -340,6 +342,27 @@ struct MoveLists {
     const int *c[4], *v[4];
     int n[4];
 };
+
+// List l of a move: staged in LDS (at l * ROW of sc / sv) by the calling
+// lanes (lane0 of nl) when at most ROW long, else read in place.
+template <int ROW = LEAF_ROW>
+__device__ __forceinline__ void stage_list(MoveLists &L, int l, const int *gc, const int *gv, int n, int *sc, int *sv,
+                                           int lane0, int nl) {
+    L.n[l] = n;
+    if (n <= ROW) {
+        sc += l * ROW;
+        sv += l * ROW;
+        for (int j = lane0; j < n; j += nl) {
+            sc[j] = gc[j];
+            sv[j] = gv[j];
+        }
+        L.c[l] = sc;
+        L.v[l] = sv;
+    } else {
+        L.c[l] = gc;
+        L.v[l] = gv;
+    }
+}
 
 // The entries at index t of the four lists (0 where absent): lower-bound
 // searches by descending powers of two, run side by side so that every step
@@ -361,14 +384,25 @@ __device__ __forceinline__ void lists_lookup(const MoveLists &L, int nmax, int t
     for (int l = 0; l < 4; ++l) out[l] = kv[l] == t ? L.v[l][lo[l]] : 0;
 }
 
+// f(x) = x ln x of the integers below FT_N, built by each workgroup in LDS
+// with the same xlogx as the direct path, so both give identical values.
+constexpr int FT_N = 512;
+__device__ __forceinline__ void ft_fill(double *ft) {
+    for (int x = threadIdx.x; x < FT_N; x += blockDim.x) ft[x] = xlogx((double)x);
+    __syncthreads();
+}
+__device__ __forceinline__ double ftx(const double *ft, int x) {
+    return (unsigned)x < (unsigned)FT_N ? ft[x] : xlogx((double)x);
+}
+
 // DL and proposal terms of one distinct neighbour block t other than r and
 // s: Mv = (M_rt, M_st, M_tr, M_ts), ko / ki the out / in ends of v into t,
 // dtt = d_t.
-__device__ __forceinline__ void block_terms(int ko, int ki, const int Mv[4], long long dtt, double eps, double epsC,
-                                            double &dL, double &qf, double &qr) {
+__device__ __forceinline__ void block_terms(const double *ft, int ko, int ki, const int Mv[4], long long dtt,
+                                            double eps, double epsC, double &dL, double &qf, double &qr) {
     const int Mrt = Mv[0], Mst = Mv[1], Mtr = Mv[2], Mts = Mv[3];
-    if (ko) dL += xlogx((double)(Mrt - ko)) - xlogx((double)Mrt) + xlogx((double)(Mst + ko)) - xlogx((double)Mst);
-    if (ki) dL += xlogx((double)(Mtr - ki)) - xlogx((double)Mtr) + xlogx((double)(Mts + ki)) - xlogx((double)Mts);
+    if (ko) dL += ftx(ft, Mrt - ko) - ftx(ft, Mrt) + ftx(ft, Mst + ko) - ftx(ft, Mst);
+    if (ki) dL += ftx(ft, Mtr - ki) - ftx(ft, Mtr) + ftx(ft, Mts + ki) - ftx(ft, Mts);
     const double kt = (double)(ko + ki);
     const double den = (double)dtt + epsC;
     qf += kt * (((double)(Mts + Mst) + eps) / den);
@@ -382,12 +416,12 @@ __device__ __forceinline__ void block_terms(int ko, int ki, const int Mv[4], lon
 struct CornerIn {
     int Mrr, Mrs, Msr, Mss, kpr, kps, ell, kout, kin, dor, dos, dir, dis;
 };
-__device__ __forceinline__ void corner_term(int cl, const CornerIn &c, double eps, double epsC, double &dL, double &qf,
-                                            double &qr) {
+__device__ __forceinline__ void corner_term(const double *ft, int cl, const CornerIn &c, double eps, double epsC,
+                                            double &dL, double &qf, double &qr) {
     const int ko_r = c.kpr & 0xffff, ki_r = c.kpr >> 16, ko_s = c.kps & 0xffff, ki_s = c.kps >> 16;
     const int drr = -ko_r - ki_r - c.ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + c.ell;
     if (cl < 8) {
-        double x, y;
+        int x, y;
         switch (cl) {
             case 0: x = c.Mrr + drr, y = c.Mrr; break;
             case 1: x = c.Mrs + drs, y = c.Mrs; break;
@@ -398,7 +432,7 @@ __device__ __forceinline__ void corner_term(int cl, const CornerIn &c, double ep
             case 6: x = c.dir - c.kin, y = c.dir; break;
             default: x = c.dis + c.kin, y = c.dis; break;
         }
-        const double f = xlogx(x) - xlogx(y);
+        const double f = ftx(ft, x) - ftx(ft, y);
         dL += cl < 4 ? f : -f;
     } else if (cl < 12) {
         const double kd = (double)(c.kout + c.kin);
@@ -432,6 +466,8 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
     __shared__ int Dt[LEAF_WAVES][SBP_LEAF_MAX], PE[LEAF_WAVES][SBP_LEAF_MAX + 1];
     __shared__ int SC[LEAF_WAVES][4 * LEAF_ROW], SV[LEAF_WAVES][4 * LEAF_ROW];
     __shared__ int CV[LEAF_WAVES][8];
+    __shared__ double FT[FT_N];
+    ft_fill(FT);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * LEAF_WAVES + wv), nw = gridDim.x * LEAF_WAVES;
     int *Kw = K[wv];
@@ -451,7 +487,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
             // edge-end keys 2 t + (1 for an in-end), in canonical end order
             int key_c[4];
             int ell = 0;
-    #pragma unroll
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int j = 64 * c + lane;
                 int key = KEY_PAD;
@@ -466,6 +502,11 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
                 }
                 key_c[c] = key;
             }
+            // row r and column r of M, staged while the proposal is drawn
+            MoveLists ML;
+            stage_list(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
+            stage_list(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
+            const int dor = bm.dout[r], dir = bm.din[r];
             // proposal: the drawn end's block comes from the lane holding its key
             const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
             const double lnu = log(draw_unit(W.w[3]));
@@ -481,8 +522,9 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
                     const int kj = __builtin_amdgcn_readlane(kc, j & 63);
                     const int t = kj == KEY_SELF ? r : kj >> 1;
                     const long long dt = (long long)bm.dout[t] + bm.din[t];
+                    const int p0 = bm.rptr[t] + bm.cptr[t], p1 = bm.rptr[t + 1] + bm.cptr[t + 1];
                     if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
-                    else s = s_draw_wave(bm, t, draw_idx(W.w[2], (uint64_t)dt));
+                    else s = s_draw_wave(bm, p0, p1, draw_idx(W.w[2], (uint64_t)dt));
                 }
             }
             if (s == r) {
@@ -491,31 +533,13 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
                 if (lane == 0) record_move(d, v, r, o, true, nb, tr);
                 continue;
             }
-            // rows r, s and columns r, s of M; the short ones staged in LDS
-            MoveLists ML;
+            // row s and column s of M
             {
-                const int b0[4] = {rb0, bm.rptr[s], cb0, bm.cptr[s]};
-                const int b1[4] = {rb1, bm.rptr[s + 1], cb1, bm.cptr[s + 1]};
-    #pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const int n = b1[l] - b0[l];
-                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + b0[l];
-                    ML.n[l] = n;
-                    if (n <= LEAF_ROW) {
-                        int *sc = SC[wv] + l * LEAF_ROW, *sv = SV[wv] + l * LEAF_ROW;
-                        for (int j = lane; j < n; j += 64) {
-                            sc[j] = gc[j];
-                            sv[j] = gv[j];
-                        }
-                        ML.c[l] = sc;
-                        ML.v[l] = sv;
-                    } else {
-                        ML.c[l] = gc;
-                        ML.v[l] = gv;
-                    }
-                }
+                const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
+                stage_list(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
+                stage_list(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
             }
-            const int dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
+            const int dos = bm.dout[s], dis = bm.din[s];
             ell = wave_sum_i32(ell);
             // sort: bitonic in registers up to 64 keys, else in LDS
             int m = 2;
@@ -530,7 +554,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
                 Kw[lane] = key;
                 wave_sync_lds();
             } else {
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (64 * c + lane < m) Kw[64 * c + lane] = key_c[c];
                 wave_sync_lds();
@@ -555,7 +579,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
             const int kk = k - 2 * ell;
             uint64_t hr = 0, hs = 0;
             int D = 0, E = 0;
-    #pragma unroll
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 64 * c + lane;
                 const int key = p < kk ? Kw[p] : KEY_PAD;
@@ -604,14 +628,14 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
                     CV[wv][4] = Mv[1];  // M_ss
                     CV[wv][5] = kp;
                 } else {
-                    block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+                    block_terms(FT, ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
                 }
             }
             wave_sync_lds();
             {
                 const CornerIn c{CV[wv][0], CV[wv][2], CV[wv][1], CV[wv][4], CV[wv][3], CV[wv][5], ell, kout, kin,
                                  dor, dos, dir, dis};
-                corner_term(lane, c, eps, epsC, dL, qf, qr);
+                corner_term(FT, lane, c, eps, epsC, dL, qf, qr);
             }
             dL = wave_sum(dL);
             qf = wave_sum(qf);
@@ -630,62 +654,94 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__re
 }
 
 constexpr int SMALL_WAVES = 4;
-constexpr int SMALL_ROW = 32;  // list entries staged per 16-lane group
+constexpr int SMALL_ROW = 32;  // list entries staged per group
 
-// Sum over an aligned group of 16 lanes (a DPP row): pairs, quads, the
-// mirrored half, then the mirrored row.  Each step adds the same two values on
-// every lane (in either order), so the whole row ends with one identical sum.
-__device__ __forceinline__ double grp16_sum(double x) {
+// Sum over an aligned group of GS = 8 or 16 lanes: pairs, quads, the mirrored
+// half row, then (16) the mirrored row.  Each step adds the same two values on
+// every lane (in either order), so the whole group ends with one identical sum.
+template <int GS>
+__device__ __forceinline__ double grp_sum(double x) {
     x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
     x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
     x += dpp_f64<0x141>(x);  // row_half_mirror
-    x += dpp_f64<0x140>(x);  // row_mirror
+    if (GS == 16) x += dpp_f64<0x140>(x);  // row_mirror
     return x;
 }
-__device__ __forceinline__ int grp16_sum_i32(int x) {
+template <int GS>
+__device__ __forceinline__ int grp_sum_i32(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
+    if (GS == 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
     return x;
 }
 
-// Four vertices with at most SMALL_K edge ends per wave, a 16-lane group each
-// with one edge end per lane: the steps of the wave kernel with group-wide
-// ballots, a 16-way proposal search run by all drawing groups together, a
-// 16-lane bitonic sort and DPP row sums.  A group left without a vertex in
-// the last round of a tile repeats group 0's and records nothing.
-__global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__restrict__ G,
+// 64 / GS vertices per wave, a GS-lane group each with one edge end per lane:
+// GS = 8 takes the vertices with at most 8 edge ends, GS = 16 those with 9 to
+// 16.  The steps of the wave kernel with group-wide ballots, a GS-way proposal
+// search run by all drawing groups together, a GS-lane bitonic sort and DPP
+// group sums.  A group left without a vertex in the last round of a tile
+// repeats group 0's and records nothing.
+template <int GS>
+__global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sweep_small(const GDev *__restrict__ G,
                                                                  const int *__restrict__ starts, int nG, int n_items,
                                                                  SparseBM bm, int *__restrict__ nb, SweepTraceDev tr) {
-    __shared__ int SC[SMALL_WAVES * 4][4 * SMALL_ROW], SV[SMALL_WAVES * 4][4 * SMALL_ROW];
-    __shared__ int Dt[SMALL_WAVES * 4][SMALL_K], PE[SMALL_WAVES * 4][SMALL_K + 1];
-    __shared__ int CV[SMALL_WAVES * 4][8];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, gi = lane >> 4, gl = lane & 15;
-    const int gs = 4 * wv + gi;  // the group's LDS slot
-    const int sh = 16 * gi;
-    const uint64_t gm = 0xffffull << sh, gbelow = lanemask_lt() & gm;
+    constexpr int NGRP = 64 / GS, KMIN = GS == SMALL_K ? SMALL_K / 2 + 1 : 0;
+    __shared__ int SC[SMALL_WAVES * NGRP][4 * SMALL_ROW], SV[SMALL_WAVES * NGRP][4 * SMALL_ROW];
+    __shared__ int Dt[SMALL_WAVES * NGRP][GS], PE[SMALL_WAVES * NGRP][GS + 1];
+    __shared__ int CV[SMALL_WAVES * NGRP][8];
+    __shared__ double FT[FT_N];
+    ft_fill(FT);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, gi = lane / GS, gl = lane % GS;
+    const int gs = NGRP * wv + gi;  // the group's LDS slot
+    const int sh = GS * gi;
+    const uint64_t gm = ((1ull << GS) - 1) << sh, gbelow = lanemask_lt() & gm;
     const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * SMALL_WAVES + wv), nw = gridDim.x * SMALL_WAVES;
     for (int tile = gw * 64; tile < n_items; tile += nw * 64) {
-        uint64_t todo = __ballot(sweep_item(G, starts, nG, n_items, tile + lane, 0, SMALL_K));
-        while (todo) {
-            int pick[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                pick[q] = todo ? __builtin_ctzll(todo) : -1;
-                todo &= todo - 1;
+        // every lane reads its own item's vertex, ends and block-r bounds once
+        // per tile; the groups take them from that lane
+        int tg = 0, tv = 0, top = 0, tko = 0, tip = 0, tki = 0, tr0 = 0, trp0 = 0, trp1 = 0, tcp0 = 0, tcp1 = 0;
+        bool tsmall = false;
+        {
+            const int it = tile + lane;
+            if (it < n_items) {
+                tg = find_graph(starts, nG, it);
+                const GDev &d = G[tg];
+                tv = it - starts[tg];
+                top = d.out_ptr[tv];
+                tko = d.out_ptr[tv + 1] - top;
+                tip = d.in_ptr[tv];
+                tki = d.in_ptr[tv + 1] - tip;
+                tsmall = (tv % d.n_batches) == d.batch && tko + tki >= KMIN && tko + tki <= GS;
+                if (tsmall) {
+                    tr0 = d.boff + d.lab[tv];
+                    trp0 = bm.rptr[tr0];
+                    trp1 = bm.rptr[tr0 + 1];
+                    tcp0 = bm.cptr[tr0];
+                    tcp1 = bm.cptr[tr0 + 1];
+                }
             }
-            const int mine = gi == 0 ? pick[0] : gi == 1 ? pick[1] : gi == 2 ? pick[2] : pick[3];
+        }
+        uint64_t todo = __ballot(tsmall);
+        while (todo) {
+            int mine = -1, first = 0;
+#pragma unroll
+            for (int q = 0; q < NGRP; ++q) {
+                const int pq = todo ? __builtin_ctzll(todo) : -1;
+                todo &= todo - 1;
+                if (q == 0) first = pq;
+                if (q == gi) mine = pq;
+            }
             const bool act = mine >= 0;
-            const int item = tile + (act ? mine : pick[0]);
-            const int g = find_graph(starts, nG, item);
+            const int src = act ? mine : first;
+            const int g = __shfl(tg, src, 64), v = __shfl(tv, src, 64);
+            const int op = __shfl(top, src, 64), kout = __shfl(tko, src, 64);
+            const int ip = __shfl(tip, src, 64), kin = __shfl(tki, src, 64);
+            const int r = __shfl(tr0, src, 64);
+            const int b0r = __shfl(trp0, src, 64), b1r = __shfl(trp1, src, 64);
+            const int c0r = __shfl(tcp0, src, 64), c1r = __shfl(tcp1, src, 64);
             const GDev &d = G[g];
-            const int v = item - starts[g];
-            const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
-            const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
             const int k = kout + kin;
-            const int r = d.boff + d.lab[v];
-            const int rb0 = bm.rptr[r], rb1 = bm.rptr[r + 1], cb0 = bm.cptr[r], cb1 = bm.cptr[r + 1];
             // the edge end of this lane: key 2 t + (1 for an in-end)
             int key = KEY_PAD, ell = 0;
             if (gl < k) {
@@ -697,41 +753,60 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__
                     key = 2 * (d.boff + d.lab[u]) + (gl < kout ? 0 : 1);
                 }
             }
-            // proposal
+            // row r and column r of M, staged while the proposal is drawn
+            MoveLists ML;
+            stage_list<SMALL_ROW>(ML, 0, bm.rcol + b0r, bm.rval + b0r, b1r - b0r, SC[gs], SV[gs], gl, GS);
+            stage_list<SMALL_ROW>(ML, 2, bm.crow + c0r, bm.cval + c0r, c1r - c0r, SC[gs], SV[gs], gl, GS);
+            const int dor = bm.dout[r], dir = bm.din[r];
+            // proposal; t's degree and running-sum range come in one round trip
             const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
             const double lnu = log(draw_unit(W.w[3]));
             int s = 0;
             long long x = -1;  // draw into t's running sums, or -1
-            int t = r;
+            int lo = 0, hi = 1;
             if (k == 0) {
                 s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
             } else {
                 const int kj = __shfl(key, sh + (int)draw_idx(W.w[0], (uint64_t)k), 64);
-                t = kj == KEY_SELF ? r : kj >> 1;
+                const int t = kj == KEY_SELF ? r : kj >> 1;
                 const long long eC = (long long)d.eps * d.C;
-                const long long dt = (long long)bm.dout[t] + bm.din[t];
-                if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
-                else x = draw_idx(W.w[2], (uint64_t)dt);
-            }
-            {
-                int lo = 0, hi = 1;
-                if (x >= 0) {
-                    lo = bm.rptr[t] + bm.cptr[t];
-                    hi = bm.rptr[t + 1] + bm.cptr[t + 1];
+                const int do_t = bm.dout[t], di_t = bm.din[t];
+                const int p0 = bm.rptr[t] + bm.cptr[t], p1 = bm.rptr[t + 1] + bm.cptr[t + 1];
+                const long long dt = (long long)do_t + di_t;
+                if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) {
+                    s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
+                } else {
+                    x = draw_idx(W.w[2], (uint64_t)dt);
+                    lo = p0;
+                    hi = p1;
                 }
-                while (__ballot(hi - lo > 1)) {
-                    const bool more = hi - lo > 1;
-                    const int st = (hi - lo + 15) >> 4;
+            }
+            // GS-way search of t's running sums by all drawing groups together;
+            // each probe also reads its block, so the last round yields s
+            {
+                bool done = x < 0;
+                while (__ballot(!done)) {
+                    const int st = (hi - lo + GS - 1) / GS;
                     const int p = min(lo + (gl + 1) * st, hi) - 1;  // the last probe is hi - 1, whose sum exceeds x
-                    const bool above = more && (long long)bm.scum[p] > x;
-                    const int f = __builtin_ctzll((__ballot(above) & gm) >> sh | 0x10000ull);
-                    if (more) {
-                        const int nlo = min(lo + f * st, hi);
-                        hi = min(lo + (f + 1) * st, hi);
-                        lo = nlo;
+                    int sc = 0, sb = 0;
+                    if (!done) {
+                        sc = bm.scum[p];
+                        sb = bm.scol[p];
+                    }
+                    const bool above = !done && (long long)sc > x;
+                    const int f = __builtin_ctzll((__ballot(above) & gm) >> sh | 1ull << GS);
+                    const int sf = __shfl(sb, sh + (f & (GS - 1)), 64);
+                    if (!done) {
+                        if (st == 1) {
+                            s = sf;
+                            done = true;
+                        } else {
+                            const int nlo = min(lo + f * st, hi);
+                            hi = min(lo + (f + 1) * st, hi);
+                            lo = nlo;
+                        }
                     }
                 }
-                if (x >= 0) s = bm.scol[lo];
             }
             const bool live = act && s != r;
             if (act && !live && gl == 0) {
@@ -739,35 +814,17 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__
                 o.s = s;
                 record_move(d, v, r, o, true, nb, tr);
             }
-            // rows r, s and columns r, s of M; the short ones staged in LDS
-            MoveLists ML;
+            // row s and column s of M
             {
-                const int b0[4] = {rb0, bm.rptr[s], cb0, bm.cptr[s]};
-                const int b1[4] = {rb1, bm.rptr[s + 1], cb1, bm.cptr[s + 1]};
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const int n = b1[l] - b0[l];
-                    const int *gc = (l < 2 ? bm.rcol : bm.crow) + b0[l], *gv = (l < 2 ? bm.rval : bm.cval) + b0[l];
-                    ML.n[l] = n;
-                    if (n <= SMALL_ROW) {
-                        int *sc = SC[gs] + l * SMALL_ROW, *sv = SV[gs] + l * SMALL_ROW;
-                        for (int j = gl; j < n; j += 16) {
-                            sc[j] = gc[j];
-                            sv[j] = gv[j];
-                        }
-                        ML.c[l] = sc;
-                        ML.v[l] = sv;
-                    } else {
-                        ML.c[l] = gc;
-                        ML.v[l] = gv;
-                    }
-                }
+                const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
+                stage_list<SMALL_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[gs], SV[gs], gl, GS);
+                stage_list<SMALL_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[gs], SV[gs], gl, GS);
             }
-            const int dor = bm.dout[r], dos = bm.dout[s], dir = bm.din[r], dis = bm.din[s];
-            ell = grp16_sum_i32(ell);
-            // 16-lane bitonic sort of the group's keys
+            const int dos = bm.dout[s], dis = bm.din[s];
+            ell = grp_sum_i32<GS>(ell);
+            // GS-lane bitonic sort of the group's keys
 #pragma unroll
-            for (int size = 2; size <= 16; size <<= 1)
+            for (int size = 2; size <= GS; size <<= 1)
 #pragma unroll
                 for (int stride = size >> 1; stride > 0; stride >>= 1) {
                     const int o = __shfl_xor(key, stride, 64);
@@ -775,7 +832,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__
                 }
             // runs of equal blocks, recorded as in the wave kernel
             const int kk = k - 2 * ell;
-            const int prev = __shfl_up(key, 1, 16);
+            const int prev = __shfl_up(key, 1, GS);
             const bool st = gl < kk && (gl == 0 || (key >> 1) != (prev >> 1));
             const uint64_t sm = __ballot(st) & gm, em = __ballot(gl < kk && !(key & 1)) & gm;
             const bool hr = (__ballot(st && (key >> 1) == r) & gm) != 0;
@@ -793,7 +850,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__
             const double epsC = (double)d.eps * (double)d.C;
             const int nmax = max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3]));
             double dL = 0.0, qf = 0.0, qr = 0.0;
-            for (int i = gl; i < Dx; i += 16) {
+            for (int i = gl; i < Dx; i += GS) {
                 int tt, ko = 0, ki = 0;
                 if (i < D) {
                     const int a0 = PE[gs][i], a1 = PE[gs][i + 1];
@@ -815,18 +872,18 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) k_sweep_small(const GDev *__
                     CV[gs][4] = Mv[1];  // M_ss
                     CV[gs][5] = ko | ki << 16;
                 } else {
-                    block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+                    block_terms(FT, ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
                 }
             }
             wave_sync_lds();
             {
                 const CornerIn c{CV[gs][0], CV[gs][2], CV[gs][1], CV[gs][4], CV[gs][3], CV[gs][5], ell, kout, kin,
                                  dor, dos, dir, dis};
-                corner_term(gl, c, eps, epsC, dL, qf, qr);
+                for (int cl = gl; cl < 12; cl += GS) corner_term(FT, cl, c, eps, epsC, dL, qf, qr);
             }
-            dL = grp16_sum(dL);
-            qf = grp16_sum(qf);
-            qr = grp16_sum(qr);
+            dL = grp_sum<GS>(dL);
+            qf = grp_sum<GS>(qf);
+            qr = grp_sum<GS>(qr);
             MoveOut o;
             o.s = s;
             o.dS = -dL;
@@ -847,6 +904,7 @@ constexpr int HUB_LDS = 8192;  // hubs with at most this many sort keys work in 
 
 // Per-workgroup LDS of the hub kernel besides the sort and item arrays.
 struct HubShared {
+    double ft[FT_N];
     double red_d[3 * (HUB_THREADS / 64)];
     int cnt_s[HUB_THREADS / 64], cnt_e[HUB_THREADS / 64], flg[HUB_THREADS / 64];
     int red[HUB_THREADS / 64];
@@ -1009,13 +1067,13 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
 #pragma unroll
         for (int l = 0; l < 4; ++l)
             if (l < nA) Mv[l] = K[l * D + i];
-        block_terms(ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
+        block_terms(H.ft, ko, ki, Mv, dtt, eps, epsC, dL, qf, qr);
     }
     __syncthreads();
     if (tid < 12) {
         const CornerIn c{H.cv[0], H.cv[2], H.cv[1], H.cv[3], H.cv[4], H.cv[5], ell, kout, kin,
                          bm.dout[r], bm.dout[s], bm.din[r], bm.din[s]};
-        corner_term(tid, c, eps, epsC, dL, qf, qr);
+        corner_term(H.ft, tid, c, eps, epsC, dL, qf, qr);
     }
     dL = wave_sum(dL);
     qf = wave_sum(qf);
@@ -1051,6 +1109,7 @@ __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restric
                                                            SweepTraceDev tr, int *__restrict__ scratch) {
     __shared__ int Ks[HUB_LDS], Dts[HUB_LDS], PEs[HUB_LDS + 1];
     __shared__ HubShared H;
+    ft_fill(H.ft);
     int *Kg = scratch + (size_t)blockIdx.x * HUB_SLOT_INTS;
     int *Dtg = Kg + SBP_MAX_DEGREE_DEV;
     int *PEg = Dtg + SBP_MAX_DEGREE_DEV;
@@ -1078,7 +1137,7 @@ __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restric
             const int t = d.boff + d.lab[u];
             const long long dt = (long long)bm.dout[t] + bm.din[t];
             if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) s = d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
-            else s = s_draw_wave(bm, t, draw_idx(W.w[2], (uint64_t)dt));
+            else s = s_draw_wave(bm, bm.rptr[t] + bm.cptr[t], bm.rptr[t + 1] + bm.cptr[t + 1], draw_idx(W.w[2], (uint64_t)dt));
         }
         if (s == r) {
             if (tid == 0) {
@@ -1550,8 +1609,10 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     ProfileScope prof("sweep_eval", s);
     if (m.n_leaf > 0) {
         const long long tiles = ((long long)m.n_leaf + 63) / 64;
-        hipLaunchKernelGGL(k_sweep_small, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0, s, dG,
-                           m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
+        hipLaunchKernelGGL(k_sweep_small<8>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0, s,
+                           dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
+        hipLaunchKernelGGL(k_sweep_small<SMALL_K>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
+                           s, dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         hipLaunchKernelGGL(k_sweep_leaf, dim3(grid_for(tiles, LEAF_WAVES, 16384)), dim3(LEAF_WAVES * 64), 0, s, dG,
                            m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         SBP_LAUNCH_CHECK();
