@@ -18,6 +18,8 @@
 //   merges (Alg. 1) ....... wave per block for scoring; application as a
 //                           parallel greedy union over the candidate
 //                           pseudoforest (pointer jumping)
+#include <mutex>
+
 #include "sbp_internal.h"
 
 namespace sbp {
@@ -459,7 +461,7 @@ __device__ __forceinline__ void corner_term(const double *ft, int cl, const Corn
 // their four M entries from one interleaved search each; the lanes holding r
 // and s publish the corner entries, and the corner, degree and Hastings terms
 // of r and s are spread over lanes 0..11 before the three wave sums.
-__global__ void __launch_bounds__(LEAF_WAVES * 64) k_sweep_leaf(const GDev *__restrict__ G, const int *__restrict__ starts,
+__global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4))) k_sweep_leaf(const GDev *__restrict__ G, const int *__restrict__ starts,
                                                                int nG, int n_items, SparseBM bm, int *__restrict__ nb,
                                                                SweepTraceDev tr) {
     __shared__ int K[LEAF_WAVES][SBP_LEAF_MAX];
@@ -683,7 +685,7 @@ __device__ __forceinline__ int grp_sum_i32(int x) {
 // group sums.  A group left without a vertex in the last round of a tile
 // repeats group 0's and records nothing.
 template <int GS>
-__global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sweep_small(const GDev *__restrict__ G,
+__global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 : 3))) k_sweep_small(const GDev *__restrict__ G,
                                                                  const int *__restrict__ starts, int nG, int n_items,
                                                                  SparseBM bm, int *__restrict__ nb, SweepTraceDev tr) {
     constexpr int NGRP = 64 / GS, KMIN = GS == SMALL_K ? SMALL_K / 2 + 1 : 0;
@@ -1603,26 +1605,64 @@ int union_dl(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch
     return 0;
 }
 
+// A second stream per device for work that overlaps the caller's stream
+// within one call, forked and joined with events; default priority.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex mu;  // one fork-join sequence at a time
+};
+constexpr int SIDE_DEVICES = 64;
+static SideStream g_side[SIDE_DEVICES];
+static std::mutex g_side_init;
+
+static int side_stream(SideStream **out) {
+    int dev = 0;
+    SBP_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SIDE_DEVICES) return fail(-5, "device index beyond the side-stream table");
+    std::lock_guard<std::mutex> lk(g_side_init);
+    SideStream &S = g_side[dev];
+    if (!S.s) {
+        SBP_HIP_CHECK(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+        SBP_HIP_CHECK(hipEventCreateWithFlags(&S.fork, hipEventDisableTiming));
+        SBP_HIP_CHECK(hipEventCreateWithFlags(&S.join, hipEventDisableTiming));
+    }
+    *out = &S;
+    return 0;
+}
+
+// Evaluation of one batch on two streams: hubs and the 9-16-end vertices on
+// the side stream, the other vertices on the caller's.  All kernels read the
+// same snapshot and write disjoint proposals; the caller's stream waits for
+// the side stream before the labels are applied.
 int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScratch &ws, const SweepTraceDev &tr,
                 hipStream_t s) {
     {
     ProfileScope prof("sweep_eval", s);
+    int rc;
+    SideStream *side = nullptr;
+    if ((rc = side_stream(&side))) return rc;
+    std::lock_guard<std::mutex> lk(side->mu);
+    SBP_HIP_CHECK(hipEventRecord(side->fork, s));
+    SBP_HIP_CHECK(hipStreamWaitEvent(side->s, side->fork, 0));
+    if (m.n_hub > 0) {
+        const int grid = m.n_hub < ws.hub_slots ? m.n_hub : ws.hub_slots;
+        hipLaunchKernelGGL(k_sweep_hub, dim3(grid), dim3(HUB_THREADS), 0, side->s, dG, m.hub, m.G, m.n_hub, bm, ws.nb,
+                           tr, ws.hub_scratch);
+        SBP_LAUNCH_CHECK();
+    }
     if (m.n_leaf > 0) {
         const long long tiles = ((long long)m.n_leaf + 63) / 64;
+        hipLaunchKernelGGL(k_sweep_small<SMALL_K>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
+                           side->s, dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         hipLaunchKernelGGL(k_sweep_small<8>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0, s,
                            dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
-        hipLaunchKernelGGL(k_sweep_small<SMALL_K>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
-                           s, dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         hipLaunchKernelGGL(k_sweep_leaf, dim3(grid_for(tiles, LEAF_WAVES, 16384)), dim3(LEAF_WAVES * 64), 0, s, dG,
                            m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         SBP_LAUNCH_CHECK();
     }
-    if (m.n_hub > 0) {
-        const int grid = m.n_hub < ws.hub_slots ? m.n_hub : ws.hub_slots;
-        hipLaunchKernelGGL(k_sweep_hub, dim3(grid), dim3(HUB_THREADS), 0, s, dG, m.hub, m.G, m.n_hub, bm, ws.nb, tr,
-                           ws.hub_scratch);
-        SBP_LAUNCH_CHECK();
-    }
+    SBP_HIP_CHECK(hipEventRecord(side->join, side->s));
+    SBP_HIP_CHECK(hipStreamWaitEvent(s, side->join, 0));
     }
     hipLaunchKernelGGL(k_sweep_apply, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G,
                        (int)m.Ntot, ws.nb);
