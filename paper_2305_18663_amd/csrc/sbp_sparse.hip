@@ -304,7 +304,7 @@ constexpr int LEAF_WAVES = 4;
 constexpr int KEY_PAD = 0x7fffffff;
 constexpr int KEY_SELF = 0x7ffffffe;  // self-loop end: after every block key, before the padding
 
-constexpr int SMALL_K = 16;  // vertices with at most this many edge ends go four or eight to a wave
+constexpr int SMALL_K = 32;  // vertices with at most this many edge ends go two to eight to a wave
 
 // Whether flat sweep item i is a vertex of the current batch with kmin..kmax
 // edge ends.
@@ -658,15 +658,17 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
 constexpr int SMALL_WAVES = 4;
 constexpr int SMALL_ROW = 32;  // list entries staged per group
 
-// Sum over an aligned group of GS = 8 or 16 lanes: pairs, quads, the mirrored
-// half row, then (16) the mirrored row.  Each step adds the same two values on
-// every lane (in either order), so the whole group ends with one identical sum.
+// Sum over an aligned group of GS = 8, 16 or 32 lanes: pairs, quads, the
+// mirrored half row, the mirrored row (16, 32), then the neighbouring row (32).
+// Each step adds the same two values on every lane (in either order), so the
+// whole group ends with one identical sum.
 template <int GS>
 __device__ __forceinline__ double grp_sum(double x) {
     x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
     x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
     x += dpp_f64<0x141>(x);  // row_half_mirror
-    if (GS == 16) x += dpp_f64<0x140>(x);  // row_mirror
+    if (GS >= 16) x += dpp_f64<0x140>(x);  // row_mirror
+    if (GS >= 32) x += __shfl_xor(x, 16, 64);
     return x;
 }
 template <int GS>
@@ -674,13 +676,14 @@ __device__ __forceinline__ int grp_sum_i32(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
-    if (GS == 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
+    if (GS >= 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
+    if (GS >= 32) x += __shfl_xor(x, 16, 64);
     return x;
 }
 
 // 64 / GS vertices per wave, a GS-lane group each with one edge end per lane:
 // GS = 8 takes the vertices with at most 8 edge ends, GS = 16 those with 9 to
-// 16.  The steps of the wave kernel with group-wide ballots, a GS-way proposal
+// 16 and GS = 32 those with 17 to 32.  The steps of the wave kernel with group-wide ballots, a GS-way proposal
 // search run by all drawing groups together, a GS-lane bitonic sort and DPP
 // group sums.  A group left without a vertex in the last round of a tile
 // repeats group 0's and records nothing.
@@ -688,7 +691,7 @@ template <int GS>
 __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 : 3))) k_sweep_small(const GDev *__restrict__ G,
                                                                  const int *__restrict__ starts, int nG, int n_items,
                                                                  SparseBM bm, int *__restrict__ nb, SweepTraceDev tr) {
-    constexpr int NGRP = 64 / GS, KMIN = GS == SMALL_K ? SMALL_K / 2 + 1 : 0;
+    constexpr int NGRP = 64 / GS, KMIN = GS == 8 ? 0 : GS / 2 + 1;
     __shared__ int SC[SMALL_WAVES * NGRP][4 * SMALL_ROW], SV[SMALL_WAVES * NGRP][4 * SMALL_ROW];
     __shared__ int Dt[SMALL_WAVES * NGRP][GS], PE[SMALL_WAVES * NGRP][GS + 1];
     __shared__ int CV[SMALL_WAVES * NGRP][8];
@@ -1631,7 +1634,7 @@ static int side_stream(SideStream **out) {
     return 0;
 }
 
-// Evaluation of one batch on two streams: hubs and the 9-16-end vertices on
+// Evaluation of one batch on two streams: hubs and the 9-32-end vertices on
 // the side stream, the other vertices on the caller's.  All kernels read the
 // same snapshot and write disjoint proposals; the caller's stream waits for
 // the side stream before the labels are applied.
@@ -1653,7 +1656,9 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     }
     if (m.n_leaf > 0) {
         const long long tiles = ((long long)m.n_leaf + 63) / 64;
-        hipLaunchKernelGGL(k_sweep_small<SMALL_K>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
+        hipLaunchKernelGGL(k_sweep_small<16>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
+                           side->s, dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
+        hipLaunchKernelGGL(k_sweep_small<32>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0,
                            side->s, dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
         hipLaunchKernelGGL(k_sweep_small<8>, dim3(grid_for(tiles, SMALL_WAVES, 16384)), dim3(SMALL_WAVES * 64), 0, s,
                            dG, m.leaf, m.G, m.n_leaf, bm, ws.nb, tr);
