@@ -159,26 +159,82 @@ __global__ void k_csc_emit(const uint64_t *__restrict__ k2, const uint64_t *__re
 }
 
 // Wave per block t: degrees, then row t of M + M^T merged in ascending column
-// (row entries first on equal columns) with running sums.
+// (row entries first on equal columns) with running sums.  When row and
+// column together fit the wave, each entry finds its merged position by a
+// search of the other list in LDS (row entry i goes to i + #column entries
+// below it, column entry j to j + #row entries at or below it); longer blocks
+// take 64 merged positions at a time by merge-path searches.
 __global__ void __launch_bounds__(BLK) k_block_rows(SparseBM bm) {
-    const int lane = threadIdx.x & 63;
+    constexpr int NW = BLK / 64;
+    __shared__ int SA[NW][64], SB[NW][64], MC[NW][64], MV[NW][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     for (int t = wave; t < bm.Ctot; t += nwaves) {
         const int r0 = bm.rptr[t], lr = bm.rptr[t + 1] - r0;
         const int c0 = bm.cptr[t], lc = bm.cptr[t + 1] - c0;
+        const int *A = bm.rcol + r0, *Av = bm.rval + r0;
+        const int *B = bm.crow + c0, *Bv = bm.cval + c0;
+        const int s0 = r0 + c0, L = lr + lc;
+        if (L <= 64) {
+            int a = 0, av = 0, b = 0, bv = 0;
+            if (lane < lr) {
+                a = A[lane];
+                av = Av[lane];
+            }
+            if (lane < lc) {
+                b = B[lane];
+                bv = Bv[lane];
+            }
+            const int so = wave_sum_i32(av), si = wave_sum_i32(bv);
+            if (lane == 0) {
+                bm.dout[t] = so;
+                bm.din[t] = si;
+            }
+            SA[wv][lane] = a;
+            SB[wv][lane] = b;
+            wave_sync_lds();
+            if (lane < lr) {
+                int lo = 0, hi = lc;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (SB[wv][mid] < a) lo = mid + 1; else hi = mid;
+                }
+                MC[wv][lane + lo] = a;
+                MV[wv][lane + lo] = av;
+            }
+            if (lane < lc) {
+                int lo = 0, hi = lr;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (SA[wv][mid] <= b) lo = mid + 1; else hi = mid;
+                }
+                MC[wv][lane + lo] = b;
+                MV[wv][lane + lo] = bv;
+            }
+            wave_sync_lds();
+            int x = lane < L ? MV[wv][lane] : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, SBP_WAVE);
+                if (lane >= o) x += y;
+            }
+            if (lane < L) {
+                bm.scol[s0 + lane] = MC[wv][lane];
+                bm.scum[s0 + lane] = x;
+            }
+            wave_sync_lds();
+            continue;
+        }
         int so = 0, si = 0;
-        for (int j = lane; j < lr; j += 64) so += bm.rval[r0 + j];
-        for (int j = lane; j < lc; j += 64) si += bm.cval[c0 + j];
+        for (int j = lane; j < lr; j += 64) so += Av[j];
+        for (int j = lane; j < lc; j += 64) si += Bv[j];
         so = wave_sum_i32(so);
         si = wave_sum_i32(si);
         if (lane == 0) {
             bm.dout[t] = so;
             bm.din[t] = si;
         }
-        const int *A = bm.rcol + r0, *Av = bm.rval + r0;
-        const int *B = bm.crow + c0, *Bv = bm.cval + c0;
-        const int s0 = r0 + c0, L = lr + lc;
         int carry = 0;
         for (int base = 0; base < L; base += 64) {
             const int q = base + lane;
@@ -657,29 +713,6 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
 
 constexpr int SMALL_WAVES = 4;
 constexpr int SMALL_ROW = 32;  // list entries staged per group
-
-// Sum over an aligned group of GS = 8, 16 or 32 lanes: pairs, quads, the
-// mirrored half row, the mirrored row (16, 32), then the neighbouring row (32).
-// Each step adds the same two values on every lane (in either order), so the
-// whole group ends with one identical sum.
-template <int GS>
-__device__ __forceinline__ double grp_sum(double x) {
-    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
-    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
-    x += dpp_f64<0x141>(x);  // row_half_mirror
-    if (GS >= 16) x += dpp_f64<0x140>(x);  // row_mirror
-    if (GS >= 32) x += __shfl_xor(x, 16, 64);
-    return x;
-}
-template <int GS>
-__device__ __forceinline__ int grp_sum_i32(int x) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
-    if (GS >= 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
-    if (GS >= 32) x += __shfl_xor(x, 16, 64);
-    return x;
-}
 
 // 64 / GS vertices per wave, a GS-lane group each with one edge end per lane:
 // GS = 8 takes the vertices with at most 8 edge ends, GS = 16 those with 9 to
