@@ -360,7 +360,7 @@ constexpr int LEAF_WAVES = 4;
 constexpr int KEY_PAD = 0x7fffffff;
 constexpr int KEY_SELF = 0x7ffffffe;  // self-loop end: after every block key, before the padding
 
-constexpr int SMALL_K = 32;  // vertices with at most this many edge ends go two to eight to a wave
+constexpr int SMALL_K = 30;  // vertices with at most this many edge ends go two to eight to a wave
 
 // Whether flat sweep item i is a vertex of the current batch with kmin..kmax
 // edge ends.
@@ -393,22 +393,26 @@ __device__ __forceinline__ int s_draw_wave(const SparseBM &bm, int lo, int hi, l
 }
 
 // Row r, row s, column r and column s of M for one move: list l holds
-// (index, value) pairs ascending by index, staged in the wave's LDS when at
-// most LEAF_ROW long, else read in place.
+// (index, value) pairs ascending by index.  A list of at most ROW entries is
+// staged in LDS whole; one of at most ROW * SPAN entries keeps in LDS only
+// the last index of every SPAN-entry window (samples, at l * ROW of samp) and
+// is otherwise read in place; a longer one is read in place.
 constexpr int LEAF_ROW = 128;
+constexpr int SPAN = 16;
 struct MoveLists {
     const int *c[4], *v[4];
     int n[4];
+    const int *samp;  // the samples of the sampled lists
+    int sampled;      // bit l: list l is sampled
 };
 
-// List l of a move: staged in LDS (at l * ROW of sc / sv) by the calling
-// lanes (lane0 of nl) when at most ROW long, else read in place.
-template <int ROW = LEAF_ROW>
+// List l of a move, staged by the calling lanes (lane0 of nl) into sc / sv.
+template <int ROW>
 __device__ __forceinline__ void stage_list(MoveLists &L, int l, const int *gc, const int *gv, int n, int *sc, int *sv,
                                            int lane0, int nl) {
     L.n[l] = n;
+    sc += l * ROW;
     if (n <= ROW) {
-        sc += l * ROW;
         sv += l * ROW;
         for (int j = lane0; j < n; j += nl) {
             sc[j] = gc[j];
@@ -419,18 +423,31 @@ __device__ __forceinline__ void stage_list(MoveLists &L, int l, const int *gc, c
     } else {
         L.c[l] = gc;
         L.v[l] = gv;
+        if (n <= ROW * SPAN) {
+            const int ns = (n + SPAN - 1) / SPAN;
+            for (int i = lane0; i < ns; i += nl) sc[i] = gc[min(SPAN * (i + 1), n) - 1];
+            L.sampled |= 1 << l;
+        }
     }
 }
 
 // The entries at index t of the four lists (0 where absent): lower-bound
 // searches by descending powers of two, run side by side so that every step
-// issues one load per list and the four share their round trips.
+// issues one load per list and the four share their round trips.  In a
+// sampled list every probe of a step of at least SPAN falls on the last entry
+// of a window (or on the list's last entry), so it reads the LDS sample.
+template <int ROW>
 __device__ __forceinline__ void lists_lookup(const MoveLists &L, int nmax, int t, int out[4]) {
     int lo[4] = {0, 0, 0, 0};
     for (int st = nmax > 0 ? 1 << (31 - __clz(nmax)) : 0; st > 0; st >>= 1) {
         int kv[4];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) kv[l] = L.n[l] > 0 ? L.c[l][min(lo[l] + st, L.n[l]) - 1] : 0;
+        for (int l = 0; l < 4; ++l) {
+            const int i = min(lo[l] + st, L.n[l]) - 1;
+            kv[l] = L.n[l] <= 0 ? 0
+                    : (st >= SPAN && ((L.sampled >> l) & 1)) ? L.samp[l * ROW + i / SPAN]
+                                                              : L.c[l][i];
+        }
 #pragma unroll
         for (int l = 0; l < 4; ++l)
             if (lo[l] + st <= L.n[l] && kv[l] < t) lo[l] += st;
@@ -562,8 +579,10 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
             }
             // row r and column r of M, staged while the proposal is drawn
             MoveLists ML;
-            stage_list(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
-            stage_list(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
+            ML.samp = SC[wv];
+            ML.sampled = 0;
+            stage_list<LEAF_ROW>(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
+            stage_list<LEAF_ROW>(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
             const int dor = bm.dout[r], dir = bm.din[r];
             // proposal: the drawn end's block comes from the lane holding its key
             const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
@@ -594,8 +613,8 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
             // row s and column s of M
             {
                 const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
-                stage_list(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
-                stage_list(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
+                stage_list<LEAF_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
+                stage_list<LEAF_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
             }
             const int dos = bm.dout[s], dis = bm.din[s];
             ell = wave_sum_i32(ell);
@@ -676,7 +695,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
                 const int kp = ko | ki << 16;
                 const long long dtt = (long long)bm.dout[t] + bm.din[t];
                 int Mv[4];
-                lists_lookup(ML, nmax, t, Mv);
+                lists_lookup<LEAF_ROW>(ML, nmax, t, Mv);
                 if (t == r) {
                     CV[wv][0] = Mv[0];  // M_rr
                     CV[wv][1] = Mv[1];  // M_sr
@@ -715,8 +734,9 @@ constexpr int SMALL_WAVES = 4;
 constexpr int SMALL_ROW = 32;  // list entries staged per group
 
 // 64 / GS vertices per wave, a GS-lane group each with one edge end per lane:
-// GS = 8 takes the vertices with at most 8 edge ends, GS = 16 those with 9 to
-// 16 and GS = 32 those with 17 to 32.  The steps of the wave kernel with group-wide ballots, a GS-way proposal
+// GS = 8 takes the vertices with at most 6 edge ends, GS = 16 those with 7 to
+// 14 and GS = 32 those with 15 to 30, so the distinct blocks plus r and s
+// never exceed the group and each lane scores one item.  The steps of the wave kernel with group-wide ballots, a GS-way proposal
 // search run by all drawing groups together, a GS-lane bitonic sort and DPP
 // group sums.  A group left without a vertex in the last round of a tile
 // repeats group 0's and records nothing.
@@ -724,7 +744,7 @@ template <int GS>
 __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 : 3))) k_sweep_small(const GDev *__restrict__ G,
                                                                  const int *__restrict__ starts, int nG, int n_items,
                                                                  SparseBM bm, int *__restrict__ nb, SweepTraceDev tr) {
-    constexpr int NGRP = 64 / GS, KMIN = GS == 8 ? 0 : GS / 2 + 1;
+    constexpr int NGRP = 64 / GS, KMIN = GS == 8 ? 0 : GS / 2 - 1, KMAX = GS - 2;
     __shared__ int SC[SMALL_WAVES * NGRP][4 * SMALL_ROW], SV[SMALL_WAVES * NGRP][4 * SMALL_ROW];
     __shared__ int Dt[SMALL_WAVES * NGRP][GS], PE[SMALL_WAVES * NGRP][GS + 1];
     __shared__ int CV[SMALL_WAVES * NGRP][8];
@@ -750,7 +770,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 tko = d.out_ptr[tv + 1] - top;
                 tip = d.in_ptr[tv];
                 tki = d.in_ptr[tv + 1] - tip;
-                tsmall = (tv % d.n_batches) == d.batch && tko + tki >= KMIN && tko + tki <= GS;
+                tsmall = (tv % d.n_batches) == d.batch && tko + tki >= KMIN && tko + tki <= KMAX;
                 if (tsmall) {
                     tr0 = d.boff + d.lab[tv];
                     trp0 = bm.rptr[tr0];
@@ -793,6 +813,8 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
             }
             // row r and column r of M, staged while the proposal is drawn
             MoveLists ML;
+            ML.samp = SC[gs];
+            ML.sampled = 0;
             stage_list<SMALL_ROW>(ML, 0, bm.rcol + b0r, bm.rval + b0r, b1r - b0r, SC[gs], SV[gs], gl, GS);
             stage_list<SMALL_ROW>(ML, 2, bm.crow + c0r, bm.cval + c0r, c1r - c0r, SC[gs], SV[gs], gl, GS);
             const int dor = bm.dout[r], dir = bm.din[r];
@@ -900,7 +922,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 }
                 const long long dtt = (long long)bm.dout[tt] + bm.din[tt];
                 int Mv[4];
-                lists_lookup(ML, nmax, tt, Mv);
+                lists_lookup<SMALL_ROW>(ML, nmax, tt, Mv);
                 if (tt == r) {
                     CV[gs][0] = Mv[0];  // M_rr
                     CV[gs][1] = Mv[1];  // M_sr
@@ -1037,6 +1059,8 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
     const int Dx = D + (hr ? 0 : 1) + (hs ? 0 : 1);
     // M entries of the items: the lists that fit in K are joined, the others searched
     MoveLists ML;
+    ML.samp = nullptr;
+    ML.sampled = 0;
     {
         const int b0[4] = {bm.rptr[r], bm.rptr[s], bm.cptr[r], bm.cptr[s]};
         const int b1[4] = {bm.rptr[r + 1], bm.rptr[s + 1], bm.cptr[r + 1], bm.cptr[s + 1]};
@@ -1090,7 +1114,7 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
         int Mv[4];
         if (corner) {
             MoveLists MA = ML;
-            lists_lookup(MA, max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3])), t, Mv);
+            lists_lookup<LEAF_ROW>(MA, max(max(ML.n[0], ML.n[1]), max(ML.n[2], ML.n[3])), t, Mv);
             if (t == r) {
                 H.cv[0] = Mv[0];
                 H.cv[1] = Mv[1];
@@ -1101,7 +1125,7 @@ __device__ __forceinline__ void hub_move(const GDev &d, const SparseBM &bm, int 
             continue;
         }
         const long long dtt = (long long)bm.dout[t] + bm.din[t];
-        lists_lookup(MS, nmax, t, Mv);
+        lists_lookup<LEAF_ROW>(MS, nmax, t, Mv);
 #pragma unroll
         for (int l = 0; l < 4; ++l)
             if (l < nA) Mv[l] = K[l * D + i];
