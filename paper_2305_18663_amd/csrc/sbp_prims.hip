@@ -155,32 +155,56 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_hist(const uint64_t *__re
     hist[(long long)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// One tile of the stable scatter: ranks as in the wave-ballot scheme (keys of
+// equal digit keep their order), but each key first goes to its digit's run
+// in an LDS copy of the tile; the tile is then written out in LDS order, so
+// a run of equal digits lands in consecutive global slots.
 template <bool VALS>
 __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(const uint64_t *__restrict__ kin,
                                                               const uint64_t *__restrict__ vin,
                                                               uint64_t *__restrict__ kout,
                                                               uint64_t *__restrict__ vout, long long n, int shift,
-                                                              long long ntiles, const long long *__restrict__ off) {
+                                                              long long ntiles, const long long *__restrict__ off,
+                                                              const int *__restrict__ hist) {
     constexpr int NW = RADIX_BLOCK / SBP_WAVE;
     __shared__ long long goff[RADIX_DIGITS];
+    __shared__ int loff[RADIX_DIGITS];
     __shared__ int run[RADIX_DIGITS];
     __shared__ int wcnt[NW][RADIX_DIGITS];
     __shared__ int wpre[NW][RADIX_DIGITS];
+    __shared__ uint64_t sk[RADIX_TILE];
+    __shared__ uint64_t sv[VALS ? RADIX_TILE : 1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     goff[t] = off[(long long)t * ntiles + blockIdx.x];
     run[t] = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
+    // tile-local start of every digit: exclusive scan of the tile's counts
+    {
+        const int c = hist[(long long)t * ntiles + blockIdx.x];
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, SBP_WAVE);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wpre[0][wave] = x;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wave; ++w) before += wpre[0][w];
+        loff[t] = before + x - c;
+    }
     __syncthreads();
     const long long base = (long long)blockIdx.x * RADIX_TILE;
+    const int tn = (int)min((long long)RADIX_TILE, n - base);
     const uint64_t below = lanemask_lt();
     for (int i = 0; i < RADIX_ITEMS; ++i) {
-        const long long idx = base + (long long)i * RADIX_BLOCK + t;
-        const bool valid = idx < n;
+        const int li = i * RADIX_BLOCK + t;
+        const bool valid = li < tn;
         uint64_t key = 0, val = 0;
         if (valid) {
-            key = kin[idx];
-            if (VALS) val = vin[idx];
+            key = kin[base + li];
+            if (VALS) val = vin[base + li];
         }
         const unsigned d = (unsigned)((key >> shift) & 0xFF);
         uint64_t eq = __ballot(valid);
@@ -206,11 +230,18 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(const uint64_t *_
         }
         __syncthreads();
         if (valid) {
-            const long long pos = goff[d] + wpre[wave][d] + rank;
-            kout[pos] = key;
-            if (VALS) vout[pos] = val;
+            const int pos = loff[d] + wpre[wave][d] + rank;
+            sk[pos] = key;
+            if (VALS) sv[pos] = val;
         }
         __syncthreads();
+    }
+    for (int li = t; li < tn; li += RADIX_BLOCK) {
+        const uint64_t key = sk[li];
+        const unsigned d = (unsigned)((key >> shift) & 0xFF);
+        const long long pos = goff[d] + (li - loff[d]);
+        kout[pos] = key;
+        if (VALS) vout[pos] = sv[li];
     }
 }
 
@@ -266,10 +297,10 @@ int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *val
         if (rc) return rc;
         if (vals)
             hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(RADIX_BLOCK), 0, s, ka, va, kb, vb,
-                               n, shift, ntiles, off);
+                               n, shift, ntiles, off, hist);
         else
             hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntiles), dim3(RADIX_BLOCK), 0, s, ka, va, kb,
-                               vb, n, shift, ntiles, off);
+                               vb, n, shift, ntiles, off, hist);
         SBP_LAUNCH_CHECK();
         uint64_t *x = ka; ka = kb; kb = x;
         x = va; va = vb; vb = x;
