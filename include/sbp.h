@@ -310,6 +310,11 @@ int sbp_engine_destroy(sbp_engine *eng);
  *   "dense_eval_workgroups"  workgroups of the dense sweep-evaluation grid
  *                            (0 = one per 64-vertex chunk, capped at 4 per CU)
  *   "dense_delta_workgroups" workgroups of the dense block-matrix update
+ *   "dense_update_moved_share" a one-batch dense sweep updates M and the end
+ *                            bytes from the moved vertices alone when at
+ *                            most value/1024 of the vertices moved (default
+ *                            128; 0..1024, or -1 for never), otherwise by a
+ *                            pass over every edge end
  * Returns SBP_E_ARG for an unknown key or a value out of range. */
 int sbp_tune(const char *key, int64_t value);
 

@@ -28,6 +28,8 @@
 // the delta, and recomputes the end bytes once at the end.
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
 #include "sbp_internal.h"
 
 namespace sbp {
@@ -79,6 +81,82 @@ __global__ void __launch_bounds__(256) k_dense_ends(GDev g, DenseBM bm) {
     }
 }
 
+// Mirror positions of every edge end, a wave per vertex v: out-end p to u is
+// the r-th copy of u in v's ascending out-list and its in-end the r-th copy of
+// v in u's ascending in-list.  Every match is checked (lists ascending, the
+// copy present); any failure clears flags[0], and so does an in-end left
+// without a mirror (k_dense_mirror_check), so the mirrors are only used when
+// they form a bijection of the edges.
+__global__ void __launch_bounds__(256) k_dense_mirror(GDev g, DenseBM bm) {
+    const int lane = threadIdx.x & 63;
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < g.n; v += (gridDim.x * blockDim.x) >> 6) {
+        const int o0 = g.out_ptr[v], o1 = g.out_ptr[v + 1];
+        for (int p = o0 + lane; p < o1; p += 64) {
+            const int u = g.out_idx[p];
+            bool ok = p == o0 || g.out_idx[p - 1] <= u;
+            int lo = o0, hi = p;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (g.out_idx[mid] < u) lo = mid + 1; else hi = mid;
+            }
+            const int i0 = g.in_ptr[u], i1 = g.in_ptr[u + 1];
+            int l2 = i0, h2 = i1;
+            while (l2 < h2) {
+                const int mid = (l2 + h2) >> 1;
+                if (g.in_idx[mid] < v) l2 = mid + 1; else h2 = mid;
+            }
+            const int q = l2 + (p - lo);
+            ok = ok && q < i1 && g.in_idx[q] == v;
+            if (ok) {
+                bm.mir_o[p] = q;
+                bm.mir_i[q] = p;
+            } else {
+                bm.mir_o[p] = -1;
+                bm.flags[0] = 0;
+            }
+        }
+        const int j0 = g.in_ptr[v], j1 = g.in_ptr[v + 1];
+        for (int q = j0 + 1 + lane; q < j1; q += 64)
+            if (g.in_idx[q - 1] > g.in_idx[q]) bm.flags[0] = 0;
+    }
+}
+__global__ void k_set_flags(int *flags) {
+    flags[0] = 1;
+    flags[1] = 0;
+}
+__global__ void k_dense_mirror_check(const DenseBM bm, int e) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < e; q += gridDim.x * blockDim.x)
+        if (bm.mir_i[q] < 0) bm.flags[0] = 0;
+}
+
+// Moved-vertex part of the end-byte update (workgroups 1.. of the final
+// kernel after a move-driven update): every moved vertex writes its new block
+// into the mirror of each of its edge ends, i.e. into the end bytes that point
+// at it.  Self-loop ends (0xff) never change.
+__device__ void mirror_bytes(const GDev &g, const DenseBM &bm, const unsigned char *__restrict__ nb, int wg, int nwg) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
+    const int v0 = (int)((long long)g.n * wg / nwg), v1 = (int)((long long)g.n * (wg + 1) / nwg);
+    for (int tb = v0 + wv * 64; tb < v1; tb += nw * 64) {
+        const int v = tb + lane;
+        const unsigned x = v < v1 ? nb[v] : 0xffu;
+        for (uint64_t todo = __ballot(x != 0xffu); todo; todo &= todo - 1) {
+            const int l = __builtin_ctzll(todo);
+            const int vv = tb + l;
+            const unsigned char xn = (unsigned char)__shfl((int)x, l, 64);
+            const int o0 = g.out_ptr[vv], o1 = g.out_ptr[vv + 1], i0 = g.in_ptr[vv], i1 = g.in_ptr[vv + 1];
+            for (int p = o0 + lane; p < o1; p += 64) {
+                const int q = bm.mir_o[p];
+                if (nlo[p] != 0xffu && (unsigned)q < (unsigned)g.e) nli[q] = xn;
+            }
+            for (int q = i0 + lane; q < i1; q += 64) {
+                const int p = bm.mir_i[q];
+                if (nli[q] != 0xffu && (unsigned)p < (unsigned)g.e) nlo[p] = xn;
+            }
+        }
+    }
+}
+
 // Vertex ranges of equal cost for a grid of G workgroups: cost(v) is the
 // number of edge ends of vertices below v plus wV per vertex below v, which is
 // monotone in v, so range w starts at the first v with cost(v) >= w/G of the
@@ -124,7 +202,12 @@ constexpr int FIN_T = 512;
 __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *__restrict__ delta,
                                                       const long long *__restrict__ stats_part,
                                                       const double *__restrict__ sum_part, int nwg,
-                                                      sbp_sweep_stats_dev *__restrict__ stats) {
+                                                      sbp_sweep_stats_dev *__restrict__ stats,
+                                                      const unsigned char *__restrict__ nbm) {
+    if (blockIdx.x > 0) {  // end bytes of the moved vertices' neighbours, after a move-driven update
+        if (nbm && bm.flags[1]) mirror_bytes(g, bm, nbm, blockIdx.x - 1, gridDim.x - 1);
+        return;
+    }
     __shared__ int so[DC], si[DC];
     __shared__ double wred[FIN_T / 64], sred[FIN_T / 64];
     __shared__ long long lred[3][FIN_T / 64];
@@ -707,7 +790,9 @@ constexpr int UPD_T = 1024;  // threads per update workgroup, one workgroup per 
 // rest are gathered.
 template <bool VEC>
 __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, const unsigned char *__restrict__ nb,
-                                                        int *__restrict__ delta, int sl) {
+                                                        int *__restrict__ delta, int sl,
+                                                        const long long *__restrict__ stats_part, int nstats,
+                                                        int moved_share) {
     const int *ub = bm.bounds;
     const bool ranged = ub[0] == (int)gridDim.x;
     const int rb0 = ranged ? ub[1 + blockIdx.x] : 0, rb1 = ranged ? ub[2 + blockIdx.x] : 0;
@@ -718,9 +803,73 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
     int *ip = op + CHU + 1;  // [CHU + 1] first in-end
     int *a0 = ip + CHU + 1;  // [CHU] old label
     int *a1 = a0 + CHU;      // [CHU] new label
-    unsigned char *nbs = (unsigned char *)smem + ((sizeof(int) * (CC + 4 * CHU + 2) + 15) & ~(size_t)15);
+    int &s_moved = a1[CHU];  // the workgroup's choice of update
+    unsigned char *nbs = (unsigned char *)smem + ((sizeof(int) * (CC + 4 * CHU + 3) + 15) & ~(size_t)15);
     unsigned char *__restrict__ nlo = bm.nl;
     unsigned char *__restrict__ nli = bm.nl + bm.nl_in;
+    // Few moves (at most moved_share / 1024 of the vertices, counted from the
+    // evaluation's partials) and verified mirrors: only the moved vertices'
+    // edges change M, so each workgroup finds the moved vertices of its share
+    // and adds their edges' changes (an edge counted by its source when the
+    // source moved, else by its target), reading old blocks from the end
+    // bytes, which this kernel then leaves untouched; the final kernel writes
+    // the new blocks into the mirrors.
+    {
+        long long acc = 0;
+        for (int w = tid; w < nstats; w += UPD_T) acc += stats_part[4 * w + 2];
+        acc = wave_sum_i64(acc);
+        long long *red = (long long *)smem;  // the histogram's space, cleared below
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            long long t = 0;
+            for (int w = 0; w < UPD_T / 64; ++w) t += red[w];
+            s_moved = bm.flags[0] == 1 && moved_share >= 0 && t * 1024 <= (long long)moved_share * g.n;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid == 0) bm.flags[1] = s_moved;
+    if (s_moved) {
+        for (int i = tid; i < CC; i += UPD_T) dl[i] = 0;
+        __syncthreads();
+        const int lane = tid & 63, wv = tid >> 6;
+        const int v0 = (int)((long long)g.n * blockIdx.x / gridDim.x);
+        const int v1 = (int)((long long)g.n * (blockIdx.x + 1) / gridDim.x);
+        for (int tb = v0 + wv * 64; tb < v1; tb += UPD_T) {
+            const int v = tb + lane;
+            const unsigned x = v < v1 ? nb[v] : 0xffu;
+            for (uint64_t todo = __ballot(x != 0xffu); todo; todo &= todo - 1) {
+                const int l = __builtin_ctzll(todo);
+                const int vv = tb + l;
+                const int xn = __shfl((int)x, l, 64);
+                const int a = g.lab[vv];
+                const int o0 = g.out_ptr[vv], o1 = g.out_ptr[vv + 1], i0 = g.in_ptr[vv], i1 = g.in_ptr[vv + 1];
+                for (int p = o0 + lane; p < o1; p += 64) {
+                    const unsigned b = nlo[p];
+                    if (b == 0xffu) {  // self-loop: (a, a) -> (x, x)
+                        atomicAdd(&dl[a * C + a], -1);
+                        atomicAdd(&dl[xn * C + xn], 1);
+                    } else {
+                        const unsigned xu = nb[g.out_idx[p]];
+                        const int bn = xu != 0xffu ? (int)xu : (int)b;
+                        atomicAdd(&dl[a * C + (int)b], -1);
+                        atomicAdd(&dl[xn * C + bn], 1);
+                    }
+                }
+                for (int q = i0 + lane; q < i1; q += 64) {
+                    const unsigned b = nli[q];
+                    if (b == 0xffu || nb[g.in_idx[q]] != 0xffu) continue;  // counted at the (moved) source
+                    atomicAdd(&dl[(int)b * C + a], -1);
+                    atomicAdd(&dl[(int)b * C + xn], 1);
+                }
+                if (lane == 0) g.lab[vv] = xn;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < CC; i += UPD_T)
+            if (dl[i]) atomicAdd(&delta[i], dl[i]);
+        return;
+    }
     for (int i = tid; i < CC; i += UPD_T) dl[i] = 0;
     for (int i = tid; i < sl / 16; i += UPD_T) ((uint4 *)nbs)[i] = ((const uint4 *)nb)[i];
     const int nchunks = (g.n + CHU - 1) / CHU;
@@ -979,6 +1128,8 @@ int dense_workgroups() {
 
 int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
 int g_delta_wgs = 512;  // workgroups of the update grid
+int g_moved_share = 128;  // move-driven update when at most this many 1024ths of the vertices moved (< 0: never)
+constexpr int MIRROR_WGS = 256;  // workgroups writing mirror bytes after a move-driven update
 
 // Grid of the evaluation for C blocks and nbc batch vertices (every
 // workgroup resident at once), and of the single-batch update.
@@ -1010,11 +1161,18 @@ int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s) {
                        bm.ftab_max);
     hipLaunchKernelGGL(k_dense_hist, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, s, g, bm.M);
     hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, delta, (const long long *)nullptr,
-                       (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr);
+                       (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr, (const unsigned char *)nullptr);
     // balanced vertex ranges for the single-batch update grid
     const int gu = update_grid(g.n, dense_workgroups());
     hipLaunchKernelGGL(k_dense_bounds, dim3(grid_for(gu + 1, 256, 16)), dim3(256), 0, s, g,
                        gu <= SBP_DENSE_BOUNDS - 2 ? gu : 0, UPDATE_VERTEX_COST, bm.bounds);
+    // mirrors of the edge ends, verified (flags[0] stays 1 only if all match)
+    hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(1), 0, s, bm.flags);
+    int rc;
+    if ((rc = fill_i32(bm.mir_i, -1, g.e, s))) return rc;
+    if (g.n > 0)
+        hipLaunchKernelGGL(k_dense_mirror, dim3(grid_for((long long)g.n * 64, 256, 4096)), dim3(256), 0, s, g, bm);
+    if (g.e > 0) hipLaunchKernelGGL(k_dense_mirror_check, dim3(grid_for(g.e, 256, 4096)), dim3(256), 0, s, bm, g.e);
     SBP_LAUNCH_CHECK();
     return dense_refresh_ends(g, bm, s);
 }
@@ -1029,7 +1187,9 @@ int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s) {
 
 template <bool ENDS, bool TRACE, int CM>
 void launch_eval(int grid, hipStream_t s, const EvalArgs &a, const SweepTraceDev &tr) {
-    hipLaunchKernelGGL((k_dense_eval<ENDS, TRACE, CM>), dim3(grid), dim3(EVAL_T), 0, s, a, tr);
+    ProfileScope prof("sweep_eval", s, true);  // the kernel's own start and stop times
+    hipExtLaunchKernelGGL((k_dense_eval<ENDS, TRACE, CM>), dim3(grid), dim3(EVAL_T), 0, s, prof.start, prof.stop, 0,
+                          a, tr);
 }
 
 // Launches the evaluation for block capacity CM; returns its grid (the number
@@ -1080,18 +1240,15 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
                       sbp_sweep_stats_dev *stats, hipStream_t s) {
     const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
     int grid;
-    {
-        ProfileScope prof("sweep_eval", s);
-        if (g.C <= 16) grid = run_eval<16>(g, bm, ws, tr, s);
-        else if (g.C <= 32) grid = run_eval<32>(g, bm, ws, tr, s);
-        else if (g.C <= 48) grid = run_eval<48>(g, bm, ws, tr, s);
-        else grid = run_eval<64>(g, bm, ws, tr, s);
-    }
+    if (g.C <= 16) grid = run_eval<16>(g, bm, ws, tr, s);
+    else if (g.C <= 32) grid = run_eval<32>(g, bm, ws, tr, s);
+    else if (g.C <= 48) grid = run_eval<48>(g, bm, ws, tr, s);
+    else grid = run_eval<64>(g, bm, ws, tr, s);
     if (g.n_batches == 1) {
         // one workgroup per CU; the decisions of the first sl vertices in the
         // LDS the workgroup leaves free
         const int ugrid = update_grid(g.n, ws.nwg);
-        const size_t fixed = (sizeof(int) * ((size_t)g.C * g.C + 4 * CHU + 2) + 15) & ~(size_t)15;
+        const size_t fixed = (sizeof(int) * ((size_t)g.C * g.C + 4 * CHU + 3) + 15) & ~(size_t)15;
         const size_t budget = (size_t)dense_lds_per_block() - 1024;
         size_t sl = budget > fixed ? budget - fixed : 0;
         if (sl > (size_t)g.n) sl = (size_t)g.n;
@@ -1100,17 +1257,22 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
         if (ugrid > 0) {
             if (vec)
                 hipLaunchKernelGGL(k_dense_update<true>, dim3(ugrid), dim3(UPD_T), fixed + sl, s, g, bm,
-                                   (const unsigned char *)ws.nb, ws.delta, (int)sl);
+                                   (const unsigned char *)ws.nb, ws.delta, (int)sl,
+                                   (const long long *)ws.stats_part, grid, g_moved_share);
             else
                 hipLaunchKernelGGL(k_dense_update<false>, dim3(ugrid), dim3(UPD_T), fixed + sl, s, g, bm,
-                                   (const unsigned char *)ws.nb, ws.delta, (int)sl);
+                                   (const unsigned char *)ws.nb, ws.delta, (int)sl,
+                                   (const long long *)ws.stats_part, grid, g_moved_share);
         }
     } else {
         hipLaunchKernelGGL(k_dense_delta, dim3(grid), dim3(256), 0, s, g, (const int *)ws.nb, ws.delta);
         hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(nbc, 256, 2048)), dim3(256), 0, s, g, (const int *)ws.nb);
     }
-    hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, ws.delta, ws.stats_part, ws.sum_part, grid,
-                       stats);
+    // one batch: workgroups 1.. write the moved vertices' mirror bytes when the
+    // update left them (a no-op after a streaming update)
+    const bool one = g.n_batches == 1;
+    hipLaunchKernelGGL(k_dense_final, dim3(one ? 1 + MIRROR_WGS : 1), dim3(FIN_T), 0, s, g, bm, ws.delta,
+                       ws.stats_part, ws.sum_part, grid, stats, one ? (const unsigned char *)ws.nb : nullptr);
     SBP_LAUNCH_CHECK();
     return 0;
 }
@@ -1118,6 +1280,10 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
 int dense_tune(const char *key, long long value) {
     if (!strcmp(key, "dense_eval_workgroups") && value >= 0) {
         g_eval_wgs = (int)value;
+        return 0;
+    }
+    if (!strcmp(key, "dense_update_moved_share") && value >= -1 && value <= 1024) {
+        g_moved_share = (int)value;
         return 0;
     }
     if (!strcmp(key, "dense_delta_workgroups") && value >= 1) {

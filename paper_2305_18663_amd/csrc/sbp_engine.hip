@@ -43,7 +43,7 @@ struct ProfRec {
 };
 static std::map<std::string, ProfRec> g_prof;
 
-ProfileScope::ProfileScope(const char *name, hipStream_t stream) : s(stream) {
+ProfileScope::ProfileScope(const char *name, hipStream_t stream, bool attach) : s(stream), attach_(attach) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     hipEvent_t a, b;
@@ -55,11 +55,16 @@ ProfileScope::ProfileScope(const char *name, hipStream_t stream) : s(stream) {
     ProfRec &r = g_prof[name];
     r.ev.push_back({a, b});
     slot = (int)r.ev.size() - 1;
-    (void)hipEventRecord(a, s);
     name_ = name;
+    if (attach_) {
+        start = a;
+        stop = b;
+    } else {
+        (void)hipEventRecord(a, s);
+    }
 }
 ProfileScope::~ProfileScope() {
-    if (slot < 0) return;
+    if (slot < 0 || attach_) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     (void)hipEventRecord(g_prof[name_].ev[slot].second, s);
 }
@@ -257,6 +262,9 @@ BMView bm_layout(void *base, int n, int e, int C) {
         v.d.nl = a.take<unsigned char>(2 * (size_t)e_al);
         v.d.nl_in = e_al;
         v.d.bounds = a.take<int>(SBP_DENSE_BOUNDS);
+        v.d.mir_o = a.take<int>((size_t)e_al);
+        v.d.mir_i = a.take<int>((size_t)e_al);
+        v.d.flags = a.take<int>(4);
         v.dl = v.d.dl;
         v.spare = a.take<long long>(1);
     } else {

@@ -28,11 +28,18 @@ int fail(int code, const std::string &msg);
 
 // ---------------------------------------------------------------- kernel timing (sbp_engine.hip)
 // Records an event pair around a launch when profiling is on.
+// Timing of one measured launch while profiling is on.  By default the scope
+// records its events on the stream around whatever it encloses; with attach,
+// it only creates them (start, stop) for the caller to hand to
+// hipExtLaunchKernelGGL, which takes the kernel's own start and stop times
+// without separate stream packets.
 struct ProfileScope {
     int slot = -1;
     hipStream_t s;
     const char *name_ = nullptr;
-    ProfileScope(const char *name, hipStream_t stream);
+    bool attach_ = false;
+    hipEvent_t start = nullptr, stop = nullptr;
+    ProfileScope(const char *name, hipStream_t stream, bool attach = false);
     ~ProfileScope();
 };
 
@@ -160,6 +167,13 @@ struct DenseBM {
     // Vertex ranges of the single-batch update: [0] = the grid they were made
     // for (0: none), [1 + w] = first vertex of workgroup w, [1 + grid] = n.
     int *bounds;
+    // The other end of the same edge for every edge end: mir_o[p] is the
+    // in-end position of out-end p, mir_i[q] the out-end position of in-end q
+    // (a bijection on each multi-edge).  flags[0] = 1 when every mirror was
+    // verified at build; flags[1] = 1 when the last single-batch update left
+    // the end bytes of the moved vertices' neighbours to the final kernel.
+    int *mir_o, *mir_i;
+    int *flags;
 };
 #define SBP_DENSE_BOUNDS 1026
 struct DenseScratch {

@@ -192,6 +192,58 @@ def test_sweep_200k_sparse_tier():
     sweep_parity(g, lab0, 500, seed=17, sweep=0)
 
 
+def chain_step(g, dg, lab, cur, C, bm, seed, k):
+    """One sweep on the device blockmodel carried over from the previous sweep,
+    checked against the oracle started from the current labels."""
+    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k)
+    near = np.abs(tr["margin"]) < 1e-9
+    force = np.full(g.n, -1, np.int8)
+    force[near] = tr["accept"][near]
+    ref = O.nodal_sweep(g, cur, C, seed, k, force=force)
+    assert np.array_equal(tr["prop"], ref["prop"]), f"proposals differ at sweep {k}"
+    assert np.array_equal(tr["accept"], ref["acc"]), f"decisions differ at sweep {k}"
+    new = lab.cpu().numpy()
+    assert np.array_equal(new, ref["lab"]), f"labels differ at sweep {k}"
+    check_coo(dg, g, new, C, bm)
+    return new
+
+
+@pytest.mark.parametrize("share", [1024, -1])
+@pytest.mark.parametrize("name,C", [("plain_1k", 10), ("multi_selfloops", 12), ("dcsbm_2k", 40)])
+def test_sweep_chain_update_modes(name, C, share):
+    # consecutive one-batch dense sweeps on one blockmodel, the update forced to
+    # the move-driven path (1024: the moved vertices' edges, mirror end bytes)
+    # or to the pass over every edge end (-1); every sweep reads the end bytes
+    # the previous update left
+    g = GRAPHS[name]()
+    dg = sbp.DeviceGraph(g)
+    cur = gen.initial_labels(g.n, C, seed=C + 11)
+    lab = sbp.labels(cur)
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    sbp.sbp_tune("dense_update_moved_share", share)
+    try:
+        for k in range(5):
+            cur = chain_step(g, dg, lab, cur, C, bm, 77, k)
+    finally:
+        sbp.sbp_tune("dense_update_moved_share", 128)
+
+
+def test_sweeps_200k_chain_default_update():
+    # 60 sweeps of the measured workload with the default update choice (the
+    # pass over every edge end while many vertices move, the move-driven path
+    # once few do), then two sweeps checked against the oracle
+    g = gen.sweep_200k()
+    C, seed = 45, 2001
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(gen.initial_labels(g.n, C, seed=seed))
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    for k in range(60):
+        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False)
+    cur = lab.cpu().numpy()
+    for k in range(60, 62):
+        cur = chain_step(g, dg, lab, cur, C, bm, seed, k)
+
+
 def hub_graph():
     """24k vertices with five hubs of 500 to 15000 edge ends over a sparse
     random background: against thousands of blocks their distinct neighbour
