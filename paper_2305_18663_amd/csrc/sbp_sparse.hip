@@ -329,20 +329,6 @@ struct MoveOut {
     bool accept;
 };
 
-// Proposal of the move of v (union block r), identical on every lane.
-__device__ __forceinline__ int propose(const GDev &d, const SparseBM &bm, int v, int r, int kout, int kin,
-                                       const Words4 &W) {
-    const int k = kout + kin;
-    const long long eC = (long long)d.eps * d.C;
-    if (k == 0) return d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
-    const int j = (int)draw_idx(W.w[0], (uint64_t)k);
-    const int u = j < kout ? d.out_idx[d.out_ptr[v] + j] : d.in_idx[d.in_ptr[v] + (j - kout)];
-    const int t = d.boff + d.lab[u];
-    const long long dt = (long long)bm.dout[t] + bm.din[t];
-    if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < eC) return d.boff + (int)draw_idx(W.w[2], (uint64_t)d.C);
-    return s_draw(bm, t, draw_idx(W.w[2], (uint64_t)dt));
-}
-
 __device__ __forceinline__ void record_move(const GDev &d, int v, int r, const MoveOut &o, bool noop, int *nb,
                                             const SweepTraceDev &tr) {
     const int u = d.voff + v;
@@ -1276,10 +1262,9 @@ __device__ double merge_dL(const SparseBM &bm, int A, int B) {
     return wave_sum(acc);
 }
 
-// merge_dL with row A and column A of M staged in LDS (ac/av: columns and
-// values of row A, la entries; rc/rv: rows and values of column A, lc
-// entries): the wave walks row B and column B in global memory and finds the
-// matching entries of A in LDS.  The same terms as merge_dL.
+// Row A and column A of M staged in LDS for the merge proposals of block A
+// (at most MERGE_ROW entries each); lds_find reads the entry at index b of a
+// staged list (0 where absent).
 constexpr int MERGE_ROW = 256;
 __device__ __forceinline__ int lds_find(const int *__restrict__ c, const int *__restrict__ v, int n, int b) {
     int lo = 0, hi = n;
@@ -1289,42 +1274,12 @@ __device__ __forceinline__ int lds_find(const int *__restrict__ c, const int *__
     }
     return (lo < n && c[lo] == b) ? v[lo] : 0;
 }
-__device__ double merge_dL_staged(const SparseBM &bm, int A, int B, const int *ac, const int *av, int la,
-                                  const int *rc, const int *rv, int lc) {
-    const int lane = threadIdx.x & 63;
-    double acc = 0.0;
-    for (int q = bm.rptr[B] + lane; q < bm.rptr[B + 1]; q += 64) {
-        const int t = bm.rcol[q];
-        if (t == A || t == B) continue;
-        const int x = lds_find(ac, av, la, t);
-        if (x) {
-            const int y = bm.rval[q];
-            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
-        }
-    }
-    for (int q = bm.cptr[B] + lane; q < bm.cptr[B + 1]; q += 64) {
-        const int t = bm.crow[q];
-        if (t == A || t == B) continue;
-        const int x = lds_find(rc, rv, lc, t);
-        if (x) {
-            const int y = bm.cval[q];
-            acc += xlogx((double)(x + y)) - xlogx((double)x) - xlogx((double)y);
-        }
-    }
-    if (lane == 0) {
-        const int a = lds_find(ac, av, la, A), b = lds_find(ac, av, la, B), e = lds_find(rc, rv, lc, B);
-        const int g = m_get(bm, B, B);
-        acc += xlogx((double)(a + b + e + g)) - xlogx((double)a) - xlogx((double)b) - xlogx((double)e) -
-               xlogx((double)g);
-        const double oa = bm.dout[A], ob = bm.dout[B], ia = bm.din[A], ib = bm.din[B];
-        acc -= xlogx(oa + ob) - xlogx(oa) - xlogx(ob);
-        acc -= xlogx(ia + ib) - xlogx(ia) - xlogx(ib);
-    }
-    return wave_sum(acc);
-}
-
-// merge_dL_staged evaluated by an aligned group of 8 lanes (gl = lane in the
-// group), each group with its own B; every lane of the group ends with the sum.
+// merge_dL with row A and column A of M staged in LDS (ac/av: columns and
+// values of row A, la entries; rc/rv: rows and values of column A, lc
+// entries), evaluated by an aligned group of 8 lanes (gl = lane in the group),
+// each group with its own B: the group walks row B and column B in global
+// memory and finds the matching entries of A in LDS.  The same terms as
+// merge_dL; every lane of the group ends with the sum.
 __device__ double merge_dL_grp8(const SparseBM &bm, int A, int B, const int *ac, const int *av, int la,
                                 const int *rc, const int *rv, int lc, int gl) {
     double acc = 0.0;
