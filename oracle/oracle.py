@@ -62,6 +62,10 @@ def lib():
         L.orc_nodal_sweep.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, I32P, ct.c_int, ct.c_uint64,
                                       ct.c_uint32, ct.c_double, ct.c_int64, ct.c_int, I32P, F64P, F64P,
                                       F64P, F64P, I8P, ct.c_void_p, I64P, ct.POINTER(ct.c_double)]
+        L.orc_nodal_sweep_h.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, I32P, ct.c_int, ct.c_uint64,
+                                        ct.c_uint32, ct.c_double, ct.c_int64, ct.c_int, ct.c_int, I32P, F64P,
+                                        F64P, F64P, F64P, I8P, ct.c_void_p, I64P, ct.POINTER(ct.c_double)]
+        L.orc_hub_order.argtypes = [ct.c_int, I32P, I32P, ct.c_int, I32P]
         L.orc_merge_scores.argtypes = [ct.c_int, I32P, I32P, I32P, ct.c_int, ct.c_uint64, ct.c_uint32,
                                        ct.c_int, ct.c_int64, I32P, F64P, F64P]
         L.orc_merge_delta.argtypes = [ct.c_int, I32P, I32P, I32P, ct.c_int, ct.c_int, ct.c_int,
@@ -122,8 +126,17 @@ def eval_move(g, lab, C, v, W, beta=3.0, eps=1):
     return dict(s=s.value, dS=dS.value, lnH=lnH.value, lnu=lnu.value, accept=bool(acc.value))
 
 
-def nodal_sweep(g, lab, C, seed, sweep, beta=3.0, eps=1, n_batches=1, force=None):
-    """One sweep; returns new labels and per-vertex trace (Alg. 2, async batches)."""
+def hub_order(g, n_hubs):
+    """The n_hubs vertices of highest degree (out + in ends), ties by smaller id."""
+    order = np.zeros(max(n_hubs, 1), np.int32)
+    if lib().orc_hub_order(g.n, g.out_ptr, g.in_ptr, n_hubs, order):
+        raise ValueError("bad hub count")
+    return order[:n_hubs]
+
+
+def nodal_sweep(g, lab, C, seed, sweep, beta=3.0, eps=1, n_batches=1, force=None, n_hubs=0):
+    """One sweep; returns new labels and per-vertex trace (Alg. 2; the n_hubs
+    highest-degree vertices one at a time first, the rest in async batches)."""
     lab = _i32(lab).copy()
     n = g.n
     prop = np.zeros(n, np.int32); dS = np.zeros(n); lnH = np.zeros(n); z = np.zeros(n); lnu = np.zeros(n)
@@ -132,8 +145,8 @@ def nodal_sweep(g, lab, C, seed, sweep, beta=3.0, eps=1, n_batches=1, force=None
     if force is not None:
         force = np.ascontiguousarray(force, dtype=np.int8)
         fptr = force.ctypes.data
-    rc = lib().orc_nodal_sweep(n, g.out_ptr, g.out_idx, g.in_ptr, g.in_idx, lab, C, seed, sweep, beta, eps,
-                               n_batches, prop, dS, lnH, z, lnu, acc, fptr, stats, ct.byref(sdS))
+    rc = lib().orc_nodal_sweep_h(n, g.out_ptr, g.out_idx, g.in_ptr, g.in_idx, lab, C, seed, sweep, beta, eps,
+                                 n_batches, n_hubs, prop, dS, lnH, z, lnu, acc, fptr, stats, ct.byref(sdS))
     if rc:
         raise ValueError("oracle sweep failed")
     return dict(lab=lab, prop=prop, dS=dS, lnH=lnH, z=z, lnu=lnu, acc=acc.astype(bool),

@@ -440,54 +440,124 @@ int orc_eval_move(int n, const int *out_ptr, const int *out_idx, const int *in_p
 }
 
 /* ------------------------------------------------------------------ */
-/* One sweep of the MCMC phase (Alg. 2 inner loop, asynchronous-Gibbs   */
-/* form of Sec. II-B / Alg. 5): batch j = {v : v mod n_batches = j}; each */
-/* batch is evaluated against the blockmodel at its start, then all its  */
-/* accepted moves are applied.  n_batches = n is sequential Alg. 2.      */
+/* One sweep of the MCMC phase (Alg. 2 inner loop) in the hybrid form    */
+/* of Sec. II-B: the n_hubs vertices of highest degree (out + in edge    */
+/* ends; ties by smaller id) move first, one at a time in that order,    */
+/* each evaluated against the assignment left by the previous one and    */
+/* applied at once (sequential Metropolis-Hastings).  The other vertices */
+/* then move in asynchronous-Gibbs batches (Sec. II-B / Alg. 5): batch   */
+/* j = {v : v mod n_batches = j, v not a hub}, evaluated against the     */
+/* blockmodel at the batch start, then all its accepted moves applied.   */
+/* n_hubs = 0 is the plain asynchronous sweep; n_batches = n is          */
+/* sequential Alg. 2.  (The paper does not fix the order of the two      */
+/* parts or the hub count; both are readings, see the design notes.)    */
 /* Words for v: counter (v, sweep, 0|1, 0).                              */
 /* force (nullable): force[v] >= 0 replaces the accept decision of v.    */
 /* stats: [proposals, self proposals, accepted, forced]                  */
 /* ------------------------------------------------------------------ */
+static int *g_deg_sort;  /* degrees for the hub order comparator */
+static int hub_cmp(const void *x, const void *y)
+{
+    const int a = *(const int *)x, b = *(const int *)y;
+    if (g_deg_sort[a] != g_deg_sort[b]) return g_deg_sort[a] > g_deg_sort[b] ? -1 : 1;
+    return a < b ? -1 : (a > b);
+}
+
+/* The first n_hubs vertices in descending degree, ties by smaller id. */
+int orc_hub_order(int n, const int *out_ptr, const int *in_ptr, int n_hubs, int *order)
+{
+    if (n_hubs < 0 || n_hubs > n) return -1;
+    int *deg = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *all = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int v = 0; v < n; ++v) {
+        deg[v] = (out_ptr[v + 1] - out_ptr[v]) + (in_ptr[v + 1] - in_ptr[v]);
+        all[v] = v;
+    }
+    g_deg_sort = deg;
+    qsort(all, (size_t)n, sizeof(int), hub_cmp);
+    memcpy(order, all, sizeof(int) * (size_t)n_hubs);
+    free(deg); free(all);
+    return 0;
+}
+
+static void record_move(const omove *mv, int v, const int *lab, const int8_t *force, int64_t *st, double *sacc,
+                        int *prop, double *dS, double *lnH, double *z, double *lnu, int8_t *acc, int *a_out)
+{
+    int a = mv->accept;
+    if (force && force[v] >= 0) { if (force[v] != a) st[3]++; a = force[v]; }
+    st[0]++;
+    if (mv->s == lab[v]) { st[1]++; a = 0; }
+    if (a) { st[2]++; *sacc += mv->dS; }
+    if (prop) prop[v] = mv->s;
+    if (dS) dS[v] = mv->dS;
+    if (lnH) lnH[v] = mv->lnH;
+    if (z) z[v] = mv->z;
+    if (lnu) lnu[v] = mv->lnu;
+    if (acc) acc[v] = (int8_t)a;
+    *a_out = a;
+}
+
+int orc_nodal_sweep_h(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx,
+                      int *lab, int C, uint64_t seed, uint32_t sweep, double beta, int64_t eps,
+                      int n_batches, int n_hubs, int *prop, double *dS, double *lnH, double *z, double *lnu,
+                      int8_t *acc, const int8_t *force, int64_t *stats, double *sum_dS)
+{
+    if (n_batches < 1) n_batches = 1;
+    if (n_batches > n) n_batches = n;
+    if (n_hubs < 0 || n_hubs > n) return -1;
+    int64_t st[4] = {0, 0, 0, 0};
+    double sacc = 0.0;
+    int *news = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int8_t *acc_local = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+    int8_t *hub = (int8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int *order = (int *)malloc(sizeof(int) * (size_t)(n_hubs > 0 ? n_hubs : 1));
+    orc_hub_order(n, out_ptr, in_ptr, n_hubs, order);
+    /* the hubs, one at a time against the current assignment */
+    for (int i = 0; i < n_hubs; ++i) {
+        const int v = order[i];
+        hub[v] = 1;
+        obm m;
+        if (obm_build(&m, n, out_ptr, out_idx, lab, C)) { free(news); free(acc_local); free(hub); free(order); return -1; }
+        uint64_t W[4];
+        orc_words(seed, (uint32_t)v, sweep, 0, 0, W);
+        omove mv;
+        eval_vertex(&m, n, out_ptr, out_idx, in_ptr, in_idx, lab, v, W, beta, eps, &mv);
+        int a;
+        record_move(&mv, v, lab, force, st, &sacc, prop, dS, lnH, z, lnu, acc, &a);
+        if (a) lab[v] = mv.s;
+        obm_free(&m);
+    }
+    /* the rest in asynchronous batches */
+    for (int j = 0; j < n_batches; ++j) {
+        obm m;
+        if (obm_build(&m, n, out_ptr, out_idx, lab, C)) { free(news); free(acc_local); free(hub); free(order); return -1; }
+        for (int v = j; v < n; v += n_batches) {
+            if (hub[v]) continue;
+            uint64_t W[4];
+            orc_words(seed, (uint32_t)v, sweep, 0, 0, W);
+            omove mv;
+            eval_vertex(&m, n, out_ptr, out_idx, in_ptr, in_idx, lab, v, W, beta, eps, &mv);
+            int a;
+            record_move(&mv, v, lab, force, st, &sacc, prop, dS, lnH, z, lnu, acc, &a);
+            news[v] = mv.s; acc_local[v] = (int8_t)a;
+        }
+        for (int v = j; v < n; v += n_batches)
+            if (!hub[v] && acc_local[v]) lab[v] = news[v];
+        obm_free(&m);
+    }
+    free(news); free(acc_local); free(hub); free(order);
+    if (stats) memcpy(stats, st, sizeof st);
+    if (sum_dS) *sum_dS = sacc;
+    return 0;
+}
+
 int orc_nodal_sweep(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx,
                     int *lab, int C, uint64_t seed, uint32_t sweep, double beta, int64_t eps,
                     int n_batches, int *prop, double *dS, double *lnH, double *z, double *lnu,
                     int8_t *acc, const int8_t *force, int64_t *stats, double *sum_dS)
 {
-    if (n_batches < 1) n_batches = 1;
-    if (n_batches > n) n_batches = n;
-    int64_t st[4] = {0, 0, 0, 0};
-    double sacc = 0.0;
-    int *news = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
-    int8_t *acc_local = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
-    for (int j = 0; j < n_batches; ++j) {
-        obm m;
-        if (obm_build(&m, n, out_ptr, out_idx, lab, C)) { free(news); free(acc_local); return -1; }
-        for (int v = j; v < n; v += n_batches) {
-            uint64_t W[4];
-            orc_words(seed, (uint32_t)v, sweep, 0, 0, W);
-            omove mv;
-            eval_vertex(&m, n, out_ptr, out_idx, in_ptr, in_idx, lab, v, W, beta, eps, &mv);
-            int a = mv.accept;
-            if (force && force[v] >= 0) { if (force[v] != a) st[3]++; a = force[v]; }
-            st[0]++;
-            if (mv.s == lab[v]) { st[1]++; a = 0; }
-            if (a) { st[2]++; sacc += mv.dS; }
-            news[v] = mv.s; acc_local[v] = (int8_t)a;
-            if (prop) prop[v] = mv.s;
-            if (dS) dS[v] = mv.dS;
-            if (lnH) lnH[v] = mv.lnH;
-            if (z) z[v] = mv.z;
-            if (lnu) lnu[v] = mv.lnu;
-            if (acc) acc[v] = (int8_t)a;
-        }
-        for (int v = j; v < n; v += n_batches)
-            if (acc_local[v]) lab[v] = news[v];
-        obm_free(&m);
-    }
-    free(news); free(acc_local);
-    if (stats) memcpy(stats, st, sizeof st);
-    if (sum_dS) *sum_dS = sacc;
-    return 0;
+    return orc_nodal_sweep_h(n, out_ptr, out_idx, in_ptr, in_idx, lab, C, seed, sweep, beta, eps, n_batches, 0,
+                             prop, dS, lnH, z, lnu, acc, force, stats, sum_dS);
 }
 
 /* ------------------------------------------------------------------ */

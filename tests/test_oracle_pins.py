@@ -521,3 +521,70 @@ def test_partition_1k_quality_and_determinism():
     assert set(a["lab"].tolist()) == set(range(a["C"]))
     # the returned DL is the DL of the returned labels
     assert a["dl"] == pytest.approx(O.description_length(g, a["lab"], a["C"]), rel=1e-13)
+
+
+# ---------------------------------------------------------------- hybrid schedule: hubs one at a time first
+def test_hub_order_by_degree_then_id():
+    g = gen.random_multigraph(30, 120, seed=4, self_loops=True)
+    deg = np.diff(g.out_ptr) + np.diff(g.in_ptr)
+    want = sorted(range(g.n), key=lambda v: (-int(deg[v]), v))
+    for k in (0, 1, 7, g.n):
+        assert list(O.hub_order(g, k)) == want[:k]
+
+
+def test_hybrid_without_hubs_is_the_async_sweep():
+    g = gen.plain_1k()
+    lab = gen.initial_labels(g.n, 10, seed=3)
+    a = O.nodal_sweep(g, lab, 10, seed=5, sweep=2, n_batches=3)
+    b = O.nodal_sweep(g, lab, 10, seed=5, sweep=2, n_batches=3, n_hubs=0)
+    for key in ("lab", "prop", "acc"):
+        assert np.array_equal(a[key], b[key])
+    assert np.array_equal(a["dS"], b["dS"])
+
+
+def test_hybrid_all_hubs_on_a_regular_graph_is_sequential_alg2():
+    # every vertex has out- and in-degree 3, so the hub order is the id order
+    # and n_hubs = n moves the vertices one at a time in id order: Alg. 2,
+    # which is also n_batches = n
+    n = 40
+    src = [v for v in range(n) for _ in range(3)]
+    dst = [(v + d) % n for v in range(n) for d in (1, 3, 7)]
+    g = gen.from_edges(n, src, dst)
+    for C, seed in ((3, 1), (6, 2)):
+        lab = gen.initial_labels(n, C, seed=seed)
+        a = O.nodal_sweep(g, lab, C, seed=seed, sweep=4, n_batches=n, beta=1.0)
+        b = O.nodal_sweep(g, lab, C, seed=seed, sweep=4, n_hubs=n, beta=1.0)
+        for key in ("lab", "prop", "acc"):
+            assert np.array_equal(a[key], b[key])
+        assert np.array_equal(a["dS"], b["dS"])
+
+
+@pytest.mark.parametrize("gi", [0, 3, 4])
+def test_hybrid_hubs_see_the_moves_before_them(gi):
+    # each hub's change of DL is the full recompute against the labels left by
+    # the hubs before it; every other vertex's against the labels after all hubs
+    g = small_graphs()[gi]
+    C, k = 3, 5
+    lab0 = gen.initial_labels(g.n, C, seed=gi + 2)
+    r = O.nodal_sweep(g, lab0, C, seed=9, sweep=1, n_hubs=k, beta=1.0)
+    cur = lab0.copy()
+    hubs = set()
+    for v in O.hub_order(g, k):
+        hubs.add(int(v))
+        s = r["prop"][v]
+        if s != cur[v]:
+            moved = cur.copy()
+            moved[v] = s
+            full = O.description_length(g, moved, C) - O.description_length(g, cur, C)
+            assert r["dS"][v] == pytest.approx(full, rel=1e-9, abs=1e-9)
+        if r["acc"][v]:
+            cur[v] = s
+    before = O.description_length(g, cur, C)
+    for v in range(g.n):
+        if v in hubs or r["prop"][v] == cur[v]:
+            continue
+        moved = cur.copy()
+        moved[v] = r["prop"][v]
+        assert r["dS"][v] == pytest.approx(O.description_length(g, moved, C) - before, rel=1e-9, abs=1e-9)
+    changed = r["lab"] != cur
+    assert np.array_equal(np.nonzero(changed)[0], np.array(sorted(v for v in range(g.n) if v not in hubs and r["acc"][v])))
