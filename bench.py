@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--skip-partition", action="store_true", help="sparse1m: merges and sweeps only")
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--calibration", type=int, default=100)
+    ap.add_argument("--hubs", type=int, default=0,
+                    help="sweep workload: the highest-degree vertices moved one at a time first (hybrid sweep)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied device-to-device first (reference size for hardware byte counters)")
     args = ap.parse_args()
@@ -293,7 +295,7 @@ def main():
     lab = sbp.labels(lab0)
     bm = sbp.sbp_build_blockmodel(dg, lab, C)
     for k in range(args.warmup):
-        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False)
+        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False, n_hubs=args.hubs)
     torch.cuda.synchronize()
 
     # timed region: K sweeps from the seeded assignment
@@ -307,7 +309,7 @@ def main():
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for k in range(args.steps):
-        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False)
+        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False, n_hubs=args.hubs)
     end.record(stream)
     torch.cuda.synchronize()
     sbp.sbp_profile_enable(False)
@@ -334,7 +336,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "directed DCSBM N=200000, 45 blocks (sizes spread 5x), E=4000000, ratio 2.5, "
                                "power-law degrees 2.1 on [1,100]; async-Gibbs sweeps from a seeded assignment",
-                   "vertices": g.n, "edges": g.e, "blocks": C, "batches_per_sweep": 1, "beta": 3.0, "eps": 1,
+                   "vertices": g.n, "edges": g.e, "blocks": C, "batches_per_sweep": 1, "hubs_per_sweep": args.hubs, "beta": 3.0, "eps": 1,
                    "dl_after": dl},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),

@@ -83,7 +83,13 @@ typedef struct sbp_sweep_params {
     int32_t n_batches;  /* >= 1; values above n are clamped to n */
     double beta;        /* inverse temperature of the acceptance test (> 0) */
     int32_t eps;        /* proposal mixing weight (>= 0), integer */
-    int32_t reserved;
+    int32_t n_hubs;     /* hybrid sweep (Sec. II-B): the n_hubs vertices of highest
+                         * degree (out + in edge ends, ties by smaller id) first
+                         * move one at a time in that order, each evaluated
+                         * against the state the previous ones left, then the
+                         * others in the n_batches snapshot batches.  0 = all
+                         * asynchronous; 0..min(n, 4096); dense tier only
+                         * (C <= SBP_DENSE_MAX_C), else SBP_E_ARG. */
 } sbp_sweep_params;
 
 /* Sweep totals, written to device memory. */

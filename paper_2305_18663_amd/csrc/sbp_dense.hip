@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
                                                       const long long *__restrict__ stats_part,
                                                       const double *__restrict__ sum_part, int nwg,
                                                       sbp_sweep_stats_dev *__restrict__ stats,
-                                                      const unsigned char *__restrict__ nbm) {
+                                                      const unsigned char *__restrict__ nbm, int extra) {
     if (blockIdx.x > 0) {  // end bytes of the moved vertices' neighbours, after a move-driven update
         if (nbm && bm.flags[1]) mirror_bytes(g, bm, nbm, blockIdx.x - 1, gridDim.x - 1);
         return;
@@ -216,13 +216,20 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
     const unsigned fmax = bm.ftab_max;
     long long a0 = 0, a1 = 0, a2 = 0;
     double sd = 0.0;
-    if (stats)
+    if (stats) {
         for (int w = tid; w < nwg; w += FIN_T) {
             a0 += stats_part[4 * w + 0];
             a1 += stats_part[4 * w + 1];
             a2 += stats_part[4 * w + 2];
             sd += sum_part[w];
         }
+        if (extra >= 0 && tid == 0) {  // the sequential pass's totals
+            a0 += stats_part[4 * extra + 0];
+            a1 += stats_part[4 * extra + 1];
+            a2 += stats_part[4 * extra + 2];
+            sd += sum_part[extra];
+        }
+    }
     if (tid < C) {
         so[tid] = 0;
         si[tid] = 0;
@@ -316,6 +323,7 @@ struct EvalArgs {
     const int *M, *dout, *din;
     const double *fM, *ftab;
     const unsigned char *nlo, *nli;
+    const int *hubrank;  // nullable: > 0 for the vertices the sequential pass already moved
     void *nb;
     long long *stats_part;
     double *sum_part;
@@ -612,7 +620,8 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                 }
                 s = unif ? (int)draw_idx(W2, (uint64_t)C) : sp;
             }
-            const bool act = valid && s != r;
+            const bool hub = valid && a.hubrank && a.hubrank[v] > 0;  // moved one at a time before this pass
+            const bool act = valid && !hub && s != r;
             if (!act) s = r;  // keeps every index below in range
             // blocks t != r, s with a neighbour: a compacted list
             unsigned char *items = L.items[grp];
@@ -720,15 +729,17 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             const double z = -a.beta * dS + lnH;
             const bool acc = act && lnu < z;
             if (gl == 0 && valid) {
-                ++n_prop;
-                if (!act) ++n_self;
+                if (!hub) {
+                    ++n_prop;
+                    if (!act) ++n_self;
+                }
                 if (acc) {
                     ++n_acc;
                     s_dS += dS;
                 }
                 if constexpr (ENDS) ((unsigned char *)a.nb)[v] = acc ? (unsigned char)s : 0xffu;
                 else ((int *)a.nb)[v] = acc ? s : -1;
-                if constexpr (TRACE) {
+                if constexpr (TRACE) if (!hub) {
                     const int uu = a.voff + v;
                     if (tr.prop) tr.prop[uu] = act ? s : r;
                     if (tr.dS) tr.dS[uu] = act ? dS : 0.0;
@@ -1025,6 +1036,269 @@ __device__ __forceinline__ long long running_e(const int *__restrict__ M, int C,
     return x;
 }
 
+// Hub order keys: descending degree (out + in edge ends), ties by smaller id.
+__global__ void k_hub_keys(GDev g, uint64_t *__restrict__ keys, int *__restrict__ hubrank) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const int deg = (g.out_ptr[v + 1] - g.out_ptr[v]) + (g.in_ptr[v + 1] - g.in_ptr[v]);
+        keys[v] = ((uint64_t)(SBP_MAX_DEGREE_DEV - deg) << 32) | (uint32_t)v;
+        hubrank[v] = 0;
+    }
+}
+__global__ void k_hub_mark(const uint64_t *__restrict__ keys, int nh, int *__restrict__ order,
+                           int *__restrict__ hubrank) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += gridDim.x * blockDim.x) {
+        const int v = (int)(uint32_t)keys[i];
+        order[i] = v;
+        hubrank[v] = i + 1;
+    }
+}
+// End bytes from the labels, only when the mirrors could not be verified (the
+// sequential pass then leaves the bytes pointing at moved hubs stale).
+__global__ void __launch_bounds__(256) k_dense_ends_unmirrored(GDev g, DenseBM bm) {
+    if (bm.flags[0] == 1) return;
+    const int lane = threadIdx.x & 63;
+    unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < g.n; v += (gridDim.x * blockDim.x) >> 6) {
+        const int o1 = g.out_ptr[v + 1], i1 = g.in_ptr[v + 1];
+        for (int j = g.out_ptr[v] + lane; j < o1; j += 64) {
+            const int u = g.out_idx[j];
+            nlo[j] = u == v ? 0xffu : (unsigned char)g.lab[u];
+        }
+        for (int j = g.in_ptr[v] + lane; j < i1; j += 64) {
+            const int u = g.in_idx[j];
+            nli[j] = u == v ? 0xffu : (unsigned char)g.lab[u];
+        }
+    }
+}
+
+// Hybrid sweep, sequential part (Sec. II-B): the hubs order[0..nh) move one at
+// a time in that order, each evaluated against the state the previous ones
+// left and applied at once.  One workgroup keeps M, the block degrees and the
+// hubs' labels in LDS; a hub's neighbour blocks come from the labels (a hub
+// from LDS: its label may have changed in this pass); the proposal and the
+// scoring are those of the evaluation kernel (one lane per block, the corner,
+// degree and Hastings terms of r and s on lanes 0-11); an accepted move
+// updates M, the degrees and the label, and writes the new block into the
+// mirrors of the hub's edge ends.  At the end M, f(M) and the degrees go back
+// to global memory and the pass's totals to statistics slot `slot`.
+constexpr int HUBS_T = 1024;
+__global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const int *__restrict__ order, int nh,
+                                                       const int *__restrict__ hubrank,
+                                                       long long *__restrict__ stats_part,
+                                                       double *__restrict__ sum_part, int slot, SweepTraceDev tr) {
+    __shared__ int Ms[DC * DC];
+    __shared__ int dos[DC], dis[DC];
+    __shared__ unsigned H[DC];  // out | in << 16 ends of the hub into each block
+    __shared__ int hl[SBP_HUBS_MAX];
+    __shared__ int s_ell, s_t0, s_dec;
+    const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63;
+    const double *tab = bm.ftab;
+    const unsigned fmax = bm.ftab_max;
+    const double eps = (double)g.eps, epsC = (double)g.eps * (double)C;
+    const long long eC = (long long)g.eps * C;
+    unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
+    for (int i = tid; i < CC; i += HUBS_T) Ms[i] = bm.M[i];
+    if (tid < C) {
+        dos[tid] = bm.dout[tid];
+        dis[tid] = bm.din[tid];
+    }
+    for (int i = tid; i < nh; i += HUBS_T) hl[i] = g.lab[order[i]];
+    long long n_prop = 0, n_self = 0, n_acc = 0;
+    double s_dS = 0.0;
+    __syncthreads();
+    for (int i = 0; i < nh; ++i) {
+        const int v = order[i], r = hl[i];
+        const int op = g.out_ptr[v], kout = g.out_ptr[v + 1] - op;
+        const int ip = g.in_ptr[v], kin = g.in_ptr[v + 1] - ip;
+        const int k = kout + kin;
+        const Words4 W = draw_words(g.seed, (uint32_t)v, g.sweep, 0u, 0u);
+        const int j0 = k > 0 ? (int)draw_idx(W.w[0], (uint64_t)k) : -1;
+        if (tid < C) H[tid] = 0;
+        if (tid == 0) {
+            s_ell = 0;
+            s_t0 = r;
+        }
+        __syncthreads();
+        // neighbour blocks: a self-loop end counts in ell (its block is r)
+        for (int j = tid; j < k; j += HUBS_T) {
+            const bool out = j < kout;
+            const int u = out ? g.out_idx[op + j] : g.in_idx[ip + (j - kout)];
+            int b = r;
+            if (u == v) {
+                if (out) atomicAdd(&s_ell, 1);
+            } else {
+                const int hr = hubrank[u];
+                b = hr > 0 ? hl[hr - 1] : g.lab[u];
+                atomicAdd(&H[b], out ? 1u : 65536u);
+            }
+            if (j == j0) s_t0 = b;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int t = lane;
+            int s;
+            if (k == 0) {
+                s = (int)draw_idx(W.w[2], (uint64_t)C);
+            } else {
+                const int t0 = s_t0;
+                const long long dt = (long long)dos[t0] + dis[t0];
+                if (draw_idx(W.w[1], (uint64_t)(dt + eC)) < (uint64_t)eC) {
+                    s = (int)draw_idx(W.w[2], (uint64_t)C);
+                } else {
+                    // the first block whose running sum of e_t0,b = M_t0,b + M_b,t0 exceeds x
+                    const long long x = (long long)draw_idx(W.w[2], (uint64_t)dt);
+                    long long e = t < C ? (long long)Ms[t0 * C + t] + Ms[t * C + t0] : 0;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const long long y = __shfl_up(e, o, 64);
+                        if (lane >= o) e += y;
+                    }
+                    const uint64_t hit = __ballot(t < C && e > x);
+                    s = hit ? __builtin_ctzll(hit) : r;
+                }
+            }
+            const double lnu = log(draw_unit(W.w[3]));
+            const bool act = s != r;
+            double dS = 0.0, lnH = 0.0, z = 0.0;
+            bool acc = false;
+            if (act) {
+                double dL = 0.0, qf = 0.0, qr = 0.0;
+                if (t < C && t != r && t != s) {
+                    const unsigned hv = H[t];
+                    const int ko = (int)(hv & 0xffffu), ki = (int)(hv >> 16);
+                    if (ko | ki) {
+                        const int Mrt = Ms[r * C + t], Mst = Ms[s * C + t], Mtr = Ms[t * C + r], Mts = Ms[t * C + s];
+                        if (ko) dL += fx(tab, fmax, Mrt - ko) - fx(tab, fmax, Mrt) + fx(tab, fmax, Mst + ko) - fx(tab, fmax, Mst);
+                        if (ki) dL += fx(tab, fmax, Mtr - ki) - fx(tab, fmax, Mtr) + fx(tab, fmax, Mts + ki) - fx(tab, fmax, Mts);
+                        const double kt = (double)(ko + ki), den = (double)(dos[t] + dis[t]) + epsC;
+                        qf += kt * (((double)(Mts + Mst) + eps) / den);
+                        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+                    }
+                }
+                if (lane < 12) {  // the blocks r and s themselves
+                    const unsigned hr = H[r], hs = H[s];
+                    const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
+                    const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
+                    const int ell = s_ell;
+                    const int Mrr = Ms[r * C + r], Mrs = Ms[r * C + s], Msr = Ms[s * C + r], Mss = Ms[s * C + s];
+                    const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
+                    const int dor = dos[r], dos_ = dos[s], dir = dis[r], dis_ = dis[s];
+                    if (lane < 8) {
+                        int x, y;
+                        switch (lane) {
+                            case 0: x = Mrr + drr, y = Mrr; break;
+                            case 1: x = Mrs + drs, y = Mrs; break;
+                            case 2: x = Msr + dsr, y = Msr; break;
+                            case 3: x = Mss + dss, y = Mss; break;
+                            case 4: x = dor - kout, y = dor; break;
+                            case 5: x = dos_ + kout, y = dos_; break;
+                            case 6: x = dir - kin, y = dir; break;
+                            default: x = dis_ + kin, y = dis_; break;
+                        }
+                        const double f = fx(tab, fmax, x) - fx(tab, fmax, y);
+                        dL += lane < 4 ? f : -f;
+                    } else {
+                        const double kd = (double)k;
+                        const double d_r = (double)dor + (double)dir, d_s = (double)dos_ + (double)dis_;
+                        int w, num;
+                        double den;
+                        switch (lane) {
+                            case 8: w = ko_r + ki_r + 2 * ell, num = Mrs + Msr, den = d_r + epsC; break;
+                            case 9: w = ko_s + ki_s, num = 2 * Mss, den = d_s + epsC; break;
+                            case 10: w = ko_r + ki_r, num = 2 * (Mrr + drr), den = d_r - kd + epsC; break;
+                            default: w = ko_s + ki_s + 2 * ell, num = Msr + dsr + Mrs + drs, den = d_s + kd + epsC; break;
+                        }
+                        if (w) {
+                            const double q = (double)w * (((double)num + eps) / den);
+                            if (lane < 10) qf += q; else qr += q;
+                        }
+                    }
+                }
+                dL = wave_sum(dL);
+                qf = wave_sum(qf);
+                qr = wave_sum(qr);
+                dS = -dL;
+                lnH = k > 0 ? log(qr) - log(qf) : 0.0;
+                z = -g.beta * dS + lnH;
+                acc = lnu < z;
+            }
+            if (lane == 0) {
+                ++n_prop;
+                if (!act) ++n_self;
+                if (acc) {
+                    ++n_acc;
+                    s_dS += dS;
+                }
+                const int uu = g.voff + v;
+                if (tr.prop) tr.prop[uu] = s;
+                if (tr.dS) tr.dS[uu] = dS;
+                if (tr.lnH) tr.lnH[uu] = lnH;
+                if (tr.margin) tr.margin[uu] = act ? z - lnu : 0.0;
+                if (tr.accept) tr.accept[uu] = acc ? 1 : 0;
+                if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) : -1;
+                s_dec = acc ? s : -1;
+            }
+        }
+        __syncthreads();
+        const int sd = s_dec;
+        if (sd >= 0) {  // apply at once
+            if (tid < C) {
+                const unsigned hv = H[tid];
+                const int ko = (int)(hv & 0xffffu), ki = (int)(hv >> 16);
+                if (ko) {
+                    atomicAdd(&Ms[r * C + tid], -ko);
+                    atomicAdd(&Ms[sd * C + tid], ko);
+                }
+                if (ki) {
+                    atomicAdd(&Ms[tid * C + r], -ki);
+                    atomicAdd(&Ms[tid * C + sd], ki);
+                }
+            }
+            if (tid == 0) {
+                const int ell = s_ell;
+                if (ell) {
+                    atomicAdd(&Ms[r * C + r], -ell);
+                    atomicAdd(&Ms[sd * C + sd], ell);
+                }
+                dos[r] -= kout;
+                dos[sd] += kout;
+                dis[r] -= kin;
+                dis[sd] += kin;
+                hl[i] = sd;
+                g.lab[v] = sd;
+            }
+            if (bm.flags[0] == 1)  // the end bytes that point at v
+                for (int j = tid; j < k; j += HUBS_T) {
+                    if (j < kout) {
+                        const int p = op + j;
+                        const int q = bm.mir_o[p];
+                        if (g.out_idx[p] != v && (unsigned)q < (unsigned)g.e) nli[q] = (unsigned char)sd;
+                    } else {
+                        const int q = ip + (j - kout);
+                        const int p = bm.mir_i[q];
+                        if (g.in_idx[q] != v && (unsigned)p < (unsigned)g.e) nlo[p] = (unsigned char)sd;
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < CC; i += HUBS_T) {
+        bm.M[i] = Ms[i];
+        bm.fM[i] = fx(tab, fmax, Ms[i]);
+    }
+    if (tid < C) {
+        bm.dout[tid] = dos[tid];
+        bm.din[tid] = dis[tid];
+    }
+    if (tid == 0) {
+        stats_part[4 * slot + 0] = n_prop;
+        stats_part[4 * slot + 1] = n_self;
+        stats_part[4 * slot + 2] = n_acc;
+        stats_part[4 * slot + 3] = 0;
+        sum_part[slot] = s_dS;
+    }
+}
+
 // Merge scoring on the dense tier, wave per block c, lane t <-> block t.
 __global__ void __launch_bounds__(256) k_dense_merge(GDev g, DenseBM bm, int *__restrict__ partner,
                                                     double *__restrict__ dS, double *__restrict__ dSl) {
@@ -1161,7 +1435,8 @@ int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s) {
                        bm.ftab_max);
     hipLaunchKernelGGL(k_dense_hist, dim3(grid_for(g.n, 256, 1024)), dim3(256), 0, s, g, bm.M);
     hipLaunchKernelGGL(k_dense_final, dim3(1), dim3(FIN_T), 0, s, g, bm, delta, (const long long *)nullptr,
-                       (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr, (const unsigned char *)nullptr);
+                       (const double *)nullptr, 0, (sbp_sweep_stats_dev *)nullptr, (const unsigned char *)nullptr,
+                       -1);
     // balanced vertex ranges for the single-batch update grid
     const int gu = update_grid(g.n, dense_workgroups());
     hipLaunchKernelGGL(k_dense_bounds, dim3(grid_for(gu + 1, 256, 16)), dim3(256), 0, s, g,
@@ -1210,6 +1485,7 @@ int run_eval(const GDev &g, const DenseBM &bm, DenseScratch &ws, const SweepTrac
     a.nlo = bm.nl;
     a.nli = bm.nl + bm.nl_in;
     a.nb = ws.nb;
+    a.hubrank = ws.hubrank;
     a.stats_part = ws.stats_part;
     a.sum_part = ws.sum_part;
     a.seed = g.seed;
@@ -1272,7 +1548,8 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
     // update left them (a no-op after a streaming update)
     const bool one = g.n_batches == 1;
     hipLaunchKernelGGL(k_dense_final, dim3(one ? 1 + MIRROR_WGS : 1), dim3(FIN_T), 0, s, g, bm, ws.delta,
-                       ws.stats_part, ws.sum_part, grid, stats, one ? (const unsigned char *)ws.nb : nullptr);
+                       ws.stats_part, ws.sum_part, grid, stats, one ? (const unsigned char *)ws.nb : nullptr,
+                       g.batch == 0 ? ws.hub_slot : -1);
     SBP_LAUNCH_CHECK();
     return 0;
 }
@@ -1296,6 +1573,27 @@ int dense_tune(const char *key, long long value) {
 int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *dS, double *dSl, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_merge, dim3((g.C * 64 + 255) / 256), dim3(256), 0, s, g, bm, partner, dS, dSl);
     SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+
+int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, uint64_t *k0, uint64_t *k1, void *temp,
+                   int *order, int *hubrank, const SweepTraceDev &tr, hipStream_t s) {
+    if (n_hubs <= 0) return 0;
+    hipLaunchKernelGGL(k_hub_keys, dim3(grid_for(g.n, 256, 4096)), dim3(256), 0, s, g, k0, hubrank);
+    SBP_LAUNCH_CHECK();
+    int rc;
+    if ((rc = radix_sort(k0, k1, nullptr, nullptr, g.n, 48, temp, s))) return rc;
+    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n_hubs, 256, 64)), dim3(256), 0, s, (const uint64_t *)k0, n_hubs,
+                       order, hubrank);
+    hipLaunchKernelGGL(k_dense_hubs, dim3(1), dim3(HUBS_T), 0, s, g, bm, (const int *)order, n_hubs,
+                       (const int *)hubrank, ws.stats_part, ws.sum_part, ws.nwg, tr);
+    if (g.n > 0)
+        hipLaunchKernelGGL(k_dense_ends_unmirrored, dim3(grid_for((long long)g.n * 64, 256, 4096)), dim3(256), 0, s,
+                           g, bm);
+    SBP_LAUNCH_CHECK();
+    ws.hubrank = hubrank;
+    ws.hub_slot = ws.nwg;
     return 0;
 }
 

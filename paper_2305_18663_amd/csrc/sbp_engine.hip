@@ -487,8 +487,8 @@ SingleWS single_layout(void *base, size_t cap, int n, int e) {
     w.dS = a.take<double>(n);
     w.nb_dense = a.take<int>(n);
     const int nwg = dense_workgroups();
-    w.stats_part = a.take<long long>(4 * (size_t)nwg);
-    w.sum_part = a.take<double>(nwg);
+    w.stats_part = a.take<long long>(4 * ((size_t)nwg + 1));  // + the hybrid sweep's sequential pass
+    w.sum_part = a.take<double>((size_t)nwg + 1);
     w.stats = a.take<sbp_sweep_stats_dev>(1);
     w.bytes = a.used;
     return w;
@@ -1010,8 +1010,12 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     if ((rc = check_graph_args(g))) return rc;
     if (!assign || !bm || !p || C < 1 || C > g->n || p->n_batches < 1 || p->eps < 0 || !(p->beta > 0))
         return fail(SBP_E_ARG, "bad sweep arguments");
+    if (p->n_hubs < 0 || p->n_hubs > std::min(g->n, SBP_HUBS_MAX))
+        return fail(SBP_E_ARG, "n_hubs must lie in [0, min(n, 4096)]");
     BMView bv = bm_layout(bm, g->n, g->e, C);
     if (bm_bytes < bv.bytes) return fail(SBP_E_SPACE, "blockmodel storage too small");
+    if (p->n_hubs > 0 && !bv.dense)
+        return fail(SBP_E_ARG, "the sequential hub pass needs the dense tier (C <= 64)");
     SingleWS w = single_layout(ws, ws_bytes, g->n, g->e);
     if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
@@ -1042,9 +1046,14 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         ds.nb = w.nb_dense;
         ds.stats_part = w.stats_part;
         ds.sum_part = w.sum_part;
+        // hybrid schedule: the hubs one at a time, then the batches without them
+        if ((rc = dense_hub_pass(d, bv.d, ds, p->n_hubs, w.u.ws.k0, w.u.ws.k1, w.u.ws.temp, w.u.ws.i0, w.hub, tr,
+                                 s)))
+            return rc;
         for (int b = 0; b < d.n_batches; ++b) {
             d.batch = b;
             if ((rc = dense_sweep_batch(d, bv.d, ds, tr, st, s))) return rc;
+            ds.hub_slot = -1;  // the first batch folded the sequential pass into the totals
         }
         if (d.n_batches > 1) return dense_refresh_ends(d, bv.d, s);
         return 0;

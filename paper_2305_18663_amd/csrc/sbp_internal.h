@@ -180,9 +180,16 @@ struct DenseScratch {
     int *delta;             // [C*C] change of M of one batch (kept zero between batches)
     int nwg;                // workgroups of the evaluation grid
     int *nb;                // [n] accepted new label, else -1 (single batch: bytes, 0xff = stays)
-    long long *stats_part;  // [nwg][4]
-    double *sum_part;       // [nwg]
+    long long *stats_part;  // [nwg + 1][4]; slot nwg: the hybrid sweep's sequential pass
+    double *sum_part;       // [nwg + 1]
+    const int *hubrank;     // nullable: > 0 for the vertices the sequential pass moved
+    int hub_slot = -1;      // the sequential pass's statistics slot (first batch), or -1
 };
+// Hybrid sweep, sequential part, dense tier: the n_hubs vertices of highest
+// degree move one at a time (order, hubrank and the sort buffers are scratch).
+int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, uint64_t *k0, uint64_t *k1, void *temp,
+                   int *order, int *hubrank, const SweepTraceDev &tr, hipStream_t s);
+constexpr int SBP_HUBS_MAX = 4096;
 int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s);
 int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr,
                       sbp_sweep_stats_dev *stats, hipStream_t s);

@@ -35,7 +35,7 @@ class Graph(ct.Structure):
 
 class SweepParams(ct.Structure):
     _fields_ = [("seed", ct.c_uint64), ("sweep", ct.c_uint32), ("n_batches", ct.c_int32), ("beta", ct.c_double),
-                ("eps", ct.c_int32), ("reserved", ct.c_int32)]
+                ("eps", ct.c_int32), ("n_hubs", ct.c_int32)]
 
 
 class SweepStats(ct.Structure):
@@ -241,9 +241,11 @@ def sbp_description_length(dg: DeviceGraph, C, bm):
 
 # ------------------------------------------------------------------ sweeps
 def sbp_nodal_sweep(dg: DeviceGraph, assign, C, bm, seed, sweep, beta=3.0, eps=1, n_batches=1, trace=True,
-                    stats=True):
-    """One sweep; assign and bm are updated in place.  Returns trace/stats dicts."""
-    p = SweepParams(seed, sweep, n_batches, beta, eps, 0)
+                    stats=True, n_hubs=0):
+    """One sweep; assign and bm are updated in place.  Returns trace/stats dicts.
+    n_hubs > 0: the hybrid sweep (the highest-degree vertices one at a time
+    first; dense tier only)."""
+    p = SweepParams(seed, sweep, n_batches, beta, eps, n_hubs)
     tr = None
     out = {}
     if trace:

@@ -112,15 +112,16 @@ def test_blockmodel_200k_full_size():
 
 
 # ---------------------------------------------------------------- sweeps
-def sweep_parity(g, lab0, C, seed, sweep, n_batches=1, beta=3.0, eps=1, dg=None):
+def sweep_parity(g, lab0, C, seed, sweep, n_batches=1, beta=3.0, eps=1, dg=None, n_hubs=0):
     dg = dg or sbp.DeviceGraph(g)
     lab = sbp.labels(lab0)
     bm = sbp.sbp_build_blockmodel(dg, lab, C)
-    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, sweep, beta=beta, eps=eps, n_batches=n_batches)
+    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, sweep, beta=beta, eps=eps, n_batches=n_batches, n_hubs=n_hubs)
     near = np.abs(tr["margin"]) < 1e-9
     force = np.full(g.n, -1, np.int8)
     force[near] = tr["accept"][near]
-    ref = O.nodal_sweep(g, lab0, C, seed, sweep, beta=beta, eps=eps, n_batches=n_batches, force=force)
+    ref = O.nodal_sweep(g, lab0, C, seed, sweep, beta=beta, eps=eps, n_batches=n_batches, force=force,
+                        n_hubs=n_hubs)
     assert np.array_equal(tr["prop"], ref["prop"]), "proposals differ"
     noop = tr["prop"] == lab0
     assert close(tr["dS"][~noop], ref["dS"][~noop]), "dS differs"
@@ -192,14 +193,14 @@ def test_sweep_200k_sparse_tier():
     sweep_parity(g, lab0, 500, seed=17, sweep=0)
 
 
-def chain_step(g, dg, lab, cur, C, bm, seed, k):
+def chain_step(g, dg, lab, cur, C, bm, seed, k, n_hubs=0):
     """One sweep on the device blockmodel carried over from the previous sweep,
     checked against the oracle started from the current labels."""
-    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k)
+    tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, n_hubs=n_hubs)
     near = np.abs(tr["margin"]) < 1e-9
     force = np.full(g.n, -1, np.int8)
     force[near] = tr["accept"][near]
-    ref = O.nodal_sweep(g, cur, C, seed, k, force=force)
+    ref = O.nodal_sweep(g, cur, C, seed, k, force=force, n_hubs=n_hubs)
     assert np.array_equal(tr["prop"], ref["prop"]), f"proposals differ at sweep {k}"
     assert np.array_equal(tr["accept"], ref["acc"]), f"decisions differ at sweep {k}"
     new = lab.cpu().numpy()
@@ -267,6 +268,70 @@ def test_sweep_hubs_many_blocks(C):
     lab0 = gen.initial_labels(g.n, C, seed=C)
     for sweep in range(3):
         sweep_parity(g, lab0, C, seed=41, sweep=sweep, dg=dg)
+
+
+# ------------------------------------------------ hybrid (hubs one at a time)
+@pytest.mark.parametrize("n_batches", [1, 3])
+@pytest.mark.parametrize("n_hubs", [1, 7, 60])
+@pytest.mark.parametrize("name,C", [("plain_1k", 10), ("multi_selfloops", 12), ("dcsbm_2k", 40)])
+def test_sweep_hybrid_hubs(name, C, n_hubs, n_batches):
+    # the n_hubs highest-degree vertices move one at a time, each against the
+    # moves of the ones before it, then the others in asynchronous batches
+    g = GRAPHS[name]()
+    lab0 = gen.initial_labels(g.n, C, seed=C + 3)
+    _, _, ref = sweep_parity(g, lab0, C, seed=31, sweep=n_hubs, n_batches=n_batches, n_hubs=n_hubs)
+    order = O.hub_order(g, n_hubs)
+    assert ref["proposals"] == g.n and len(order) == n_hubs
+
+
+def test_sweep_hybrid_all_hubs_is_sequential():
+    # every vertex a hub: the sequential sweep (one vertex per batch, in
+    # degree order), on multi-edges and self-loops, dense blocks up to 64
+    g = gen.random_multigraph(90, 400, seed=3, self_loops=True)
+    for C in (3, 64):
+        lab0 = gen.initial_labels(g.n, C, seed=C)
+        sweep_parity(g, lab0, C, seed=5, sweep=1, beta=1.0, n_hubs=g.n)
+
+
+def test_sweep_hybrid_chain():
+    # consecutive hybrid sweeps on one blockmodel, the update forced to the
+    # move-driven path and to the pass over every edge end in turn: the hubs'
+    # moves reach the next evaluation only through the end bytes
+    g = GRAPHS["dcsbm_2k"]()
+    C = 40
+    dg = sbp.DeviceGraph(g)
+    cur = gen.initial_labels(g.n, C, seed=5)
+    lab = sbp.labels(cur)
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    try:
+        for k in range(6):
+            sbp.sbp_tune("dense_update_moved_share", 1024 if k % 2 else -1)
+            cur = chain_step(g, dg, lab, cur, C, bm, 13, k, n_hubs=25)
+    finally:
+        sbp.sbp_tune("dense_update_moved_share", 128)
+
+
+def test_sweep_hybrid_200k():
+    g = gen.sweep_200k()
+    lab0 = gen.initial_labels(g.n, 45, seed=2001)
+    sweep_parity(g, lab0, 45, seed=2001, sweep=0, n_hubs=16)
+
+
+def test_sweep_hybrid_rejects():
+    g = GRAPHS["plain_1k"]()
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(gen.initial_labels(g.n, 70, seed=1))
+    bm = sbp.sbp_build_blockmodel(dg, lab, 70)
+    before = lab.cpu().numpy().copy()
+    with pytest.raises(sbp.SbpError):  # sparse tier (C > 64)
+        sbp.sbp_nodal_sweep(dg, lab, 70, bm, 1, 0, n_hubs=4)
+    lab10 = sbp.labels(gen.initial_labels(g.n, 10, seed=1))
+    bm10 = sbp.sbp_build_blockmodel(dg, lab10, 10)
+    with pytest.raises(sbp.SbpError):  # more hubs than vertices
+        sbp.sbp_nodal_sweep(dg, lab10, 10, bm10, 1, 0, n_hubs=g.n + 1)
+    with pytest.raises(sbp.SbpError):
+        sbp.sbp_nodal_sweep(dg, lab10, 10, bm10, 1, 0, n_hubs=-1)
+    assert np.array_equal(lab.cpu().numpy(), before)
 
 
 # ---------------------------------------------------------------- merges
