@@ -15,7 +15,9 @@ within:between ratio near 2 and Dirichlet block sizes, Sec. IV-A):
    theta_out; its target block is the source's block with probability
    ratio/(1+ratio), otherwise another block proportional to that block's total
    theta_in; its target vertex is proportional to theta_in inside the block.
-   Self-loops are redrawn; multi-edges are kept.
+   Self-loops are redrawn; an edge whose target block holds no in-weight
+   besides its source's takes another block, drawn as a between-block
+   target.  Multi-edges are kept.
 4. Vertex ids are randomly permuted so planted blocks are not contiguous.
 
 Graphs are returned as int32 CSR (out-edges) and CSC (in-edges), neighbours
@@ -95,25 +97,40 @@ def dcsbm(sizes, e, ratio, seed, gamma=2.1, kmin=1, kmax=100) -> Graph:
     rng = np.random.default_rng(seed)
     sizes = np.asarray(sizes, dtype=np.int64)
     n = int(sizes.sum())
-    nb = sizes.size
-    block = np.repeat(np.arange(nb, dtype=np.int64), sizes)  # contiguous before permutation
     th_out = _power_law(rng, n, gamma, kmin, kmax)
     th_in = _power_law(rng, n, gamma, kmin, kmax)
+    return _dcsbm_draw(rng, sizes, th_out, th_in, e, ratio)
+
+
+def _dcsbm_draw(rng, sizes, th_out, th_in, e, ratio) -> Graph:
+    """Steps 3 and 4 of the module docstring for given vertex weights."""
+    n = int(sizes.sum())
+    nb = sizes.size
+    block = np.repeat(np.arange(nb, dtype=np.int64), sizes)  # contiguous before permutation
     p_in = ratio / (1.0 + ratio)
 
     src = _draw_prop(rng, np.cumsum(th_out), e)
     sb = block[src]
     tb = sb.copy()
     between = rng.random(e) >= p_in
+    wblk = np.bincount(block, weights=th_in, minlength=nb)
+    cumb = np.cumsum(wblk)
+    pos_in = np.bincount(block[th_in > 0], minlength=nb)  # vertices with in-weight, per block
     if nb > 1:
-        wblk = np.bincount(block, weights=th_in, minlength=nb)
-        cumb = np.cumsum(wblk)
         idx = np.nonzero(between)[0]
         while idx.size:
             draw = _draw_prop(rng, cumb, idx.size)
             ok = draw != sb[idx]
             tb[idx[ok]] = draw[ok]
             idx = idx[~ok]
+    idx = np.nonzero(wblk[tb] <= 0)[0]  # a block without in-weight takes no edges
+    if idx.size and nb == 1:
+        raise ValueError("no vertex has in-weight")
+    while idx.size:
+        draw = _draw_prop(rng, cumb, idx.size)
+        ok = draw != sb[idx]
+        tb[idx[ok]] = draw[ok]
+        idx = idx[~ok]
     # target vertex proportional to theta_in within the target block
     cum_in = np.cumsum(th_in)
     bstart = np.concatenate([[0], np.cumsum(sizes)[:-1]])
@@ -127,9 +144,20 @@ def dcsbm(sizes, e, ratio, seed, gamma=2.1, kmin=1, kmax=100) -> Graph:
         d = np.searchsorted(cum_in, u, side="right").clip(bstart[b_], bstart[b_] + sizes[b_] - 1)
         dst[pending] = d
         pending = pending[d == src[pending]]  # redraw self-loops
-        if pending.size and np.all(sizes[tb[pending]] == 1):
-            # a singleton block can only self-loop: fall back to another block's vertex
-            raise ValueError("singleton block forces a self-loop")
+        if pending.size:
+            # a target block with no in-weight besides the source's can only
+            # give a self-loop: such an edge takes another block instead
+            sp = src[pending]
+            stuck = pos_in[tb[pending]] - (th_in[sp] > 0) <= 0
+            if stuck.any():
+                if nb == 1:
+                    raise ValueError("one block with one target: every edge would be a self-loop")
+                idx = pending[stuck]
+                while idx.size:
+                    draw = _draw_prop(rng, cumb, idx.size)
+                    ok = draw != sb[idx]
+                    tb[idx[ok]] = draw[ok]
+                    idx = idx[~ok]
     perm = rng.permutation(n)
     planted = np.empty(n, dtype=np.int32)
     planted[perm] = block
@@ -139,6 +167,72 @@ def dcsbm(sizes, e, ratio, seed, gamma=2.1, kmin=1, kmax=100) -> Graph:
 # --------------------------------------------------------------------------
 # Workload recipes (sizes and seeds of the paper-shaped synthetic inputs)
 # --------------------------------------------------------------------------
+
+# The paper's exhaustive parameter-search families (Sec. IV-A, table of
+# synthetic graphs): truncated min degree, truncated max degree, duplicated
+# degree sequence, communities, edges.  Every family starts from 22,599
+# vertices; vertices left without edges are dropped, as the table's smaller
+# vertex counts for the untruncated-min families show.
+ABLATION = {
+    "TTT33": (True, True, True, 33, 899283), "TTT150": (True, True, True, 150, 826861),
+    "TTF33": (True, True, False, 33, 452232), "TTF150": (True, True, False, 150, 421317),
+    "TFT33": (True, False, True, 33, 1059970), "TFT150": (True, False, True, 150, 912644),
+    "TFF33": (True, False, False, 33, 540410), "TFF150": (True, False, False, 150, 471071),
+    "FTT33": (False, True, True, 33, 79683), "FTT150": (False, True, True, 150, 78226),
+    "FTF33": (False, True, False, 33, 39719), "FTF150": (False, True, False, 150, 38408),
+    "FFT33": (False, False, True, 33, 83939), "FFT150": (False, False, True, 150, 81298),
+    "FFF33": (False, False, False, 33, 41378), "FFF150": (False, False, False, 150, 40835),
+}
+ABLATION_N = 22599
+ABLATION_RATIO = 2.0
+
+
+def ablation_bounds(tmin: bool, tmax: bool, n: int = ABLATION_N):
+    """Degree range of a family: [10, 100] truncated; min 1 and max n/20 when not."""
+    return (10 if tmin else 1), (100 if tmax else max(100, n // 20))
+
+
+def ablation_degrees(rng, n, tmin, tmax, dup, gamma=2.1):
+    """Out- and in-degree sequences of one family.
+
+    A total-degree sequence k is drawn from PL(gamma) on the family's range.
+    Duplicated: k serves as both the out- and the in-degree sequence (so every
+    vertex has in-degree = out-degree >= the minimum).  Split: each unit of k
+    goes to the out- or the in-degree at random (Binomial(k, 1/2)), so a vertex
+    may have total degree 1.
+    """
+    kmin, kmax = ablation_bounds(tmin, tmax, n)
+    k = _power_law(rng, n, gamma, kmin, kmax)
+    if dup:
+        return k.copy(), k.copy()
+    kout = rng.binomial(k.astype(np.int64), 0.5).astype(np.float64)
+    return kout, k - kout
+
+
+def ablation_graph(name: str, seed: int = 4000, scale: float = 1.0) -> Graph:
+    """One draw of an ablation family, vertices and edges scaled by `scale`.
+
+    Block sizes are Dirichlet(2) over the family's community count; vertex
+    weights come from ablation_degrees; edges as in the module docstring with
+    within:between ratio 2 and the family's edge count; vertices without
+    edges are then removed (ids renumbered in order, planted labels kept).
+    """
+    tmin, tmax, dup, nb, e = ABLATION[name]
+    rng = np.random.default_rng(seed)
+    n = max(nb, int(round(ABLATION_N * scale)))
+    w = rng.dirichlet(np.full(nb, 2.0))
+    sizes = np.maximum(2, np.floor(w * n)).astype(np.int64)
+    sizes[np.argmax(sizes)] += n - sizes.sum()
+    th_out, th_in = ablation_degrees(rng, n, tmin, tmax, dup)
+    g = _dcsbm_draw(rng, sizes, th_out, th_in, int(round(e * scale)), ABLATION_RATIO)
+    kout, kin = g.degrees()
+    keep = (kout + kin) > 0
+    if keep.all():
+        return g
+    new_id = np.cumsum(keep) - 1
+    src, dst = g.edges()
+    return from_edges(int(keep.sum()), new_id[src], new_id[dst], g.planted[keep], nb)
+
 
 def plain_1k(seed: int = 1000) -> Graph:
     """1,000 vertices, 10 equal planted blocks, 8,000 edges, ratio 2.5, PL(2.1,[1,100])."""
