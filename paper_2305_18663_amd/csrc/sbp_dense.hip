@@ -1036,7 +1036,9 @@ __device__ __forceinline__ long long running_e(const int *__restrict__ M, int C,
     return x;
 }
 
-// Hub order keys: descending degree (out + in edge ends), ties by smaller id.
+// Hub order keys: descending degree (out + in edge ends) in bits 32-46, the
+// vertex id below.  The keys are written in id order and sorted stably on the
+// degree bits alone, so ties keep ascending ids.
 __global__ void k_hub_keys(GDev g, uint64_t *__restrict__ keys, int *__restrict__ hubrank) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
         const int deg = (g.out_ptr[v + 1] - g.out_ptr[v]) + (g.in_ptr[v + 1] - g.in_ptr[v]);
@@ -1044,14 +1046,70 @@ __global__ void k_hub_keys(GDev g, uint64_t *__restrict__ keys, int *__restrict_
         hubrank[v] = 0;
     }
 }
-__global__ void k_hub_mark(const uint64_t *__restrict__ keys, int nh, int *__restrict__ order,
-                           int *__restrict__ hubrank) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += gridDim.x * blockDim.x) {
-        const int v = (int)(uint32_t)keys[i];
-        order[i] = v;
-        hubrank[v] = i + 1;
+// The first nh sorted vertices: order, rank (1-based), out | in << 16 end
+// counts and the offsets of their edge ends in the code arrays (an exclusive
+// scan of the degrees, one workgroup, nh <= SBP_HUBS_MAX).
+constexpr int MARK_T = 1024;
+__global__ void __launch_bounds__(MARK_T) k_hub_mark(GDev g, const uint64_t *__restrict__ keys, int nh,
+                                                     int *__restrict__ order, int *__restrict__ hubrank,
+                                                     int *__restrict__ kk, int *__restrict__ hoff) {
+    __shared__ int part[MARK_T];
+    constexpr int PER = SBP_HUBS_MAX / MARK_T;
+    const int tid = threadIdx.x;
+    int deg[PER], sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid * PER + q;
+        deg[q] = 0;
+        if (i < nh) {
+            const int v = (int)(uint32_t)keys[i];
+            const int ko = g.out_ptr[v + 1] - g.out_ptr[v], ki = g.in_ptr[v + 1] - g.in_ptr[v];
+            order[i] = v;
+            hubrank[v] = i + 1;
+            kk[i] = ko | (ki << 16);
+            deg[q] = ko + ki;
+        }
+        sum += deg[q];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < MARK_T; o <<= 1) {  // inclusive scan of the thread sums
+        const int x = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid * PER + q;
+        if (i < nh) hoff[i] = run;
+        run += deg[q];
+    }
+    if (tid == MARK_T - 1) hoff[nh] = part[MARK_T - 1];
+}
+// Neighbour codes of every hub edge end, contiguous per hub (a workgroup per
+// hub): the far end's block (>= 0) for a vertex that is no hub (its label
+// does not change during the pass), -rank for a hub, HUB_SELF for a self-loop;
+// mpos holds the position of the mirror end byte (in-ends for out-ends and
+// the reverse).
+constexpr int HUB_SELF = -(1 << 20);
+__global__ void __launch_bounds__(256) k_hub_codes(GDev g, DenseBM bm, const int *__restrict__ order,
+                                                   const int *__restrict__ kk, const int *__restrict__ hoff,
+                                                   const int *__restrict__ hubrank, int *__restrict__ codes,
+                                                   int *__restrict__ mpos) {
+    const int i = blockIdx.x, v = order[i], kout = kk[i] & 0xffff, k = kout + (kk[i] >> 16), h0 = hoff[i];
+    const int op = g.out_ptr[v], ip = g.in_ptr[v];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        const bool out = j < kout;
+        const int p = out ? op + j : ip + (j - kout);
+        const int u = out ? g.out_idx[p] : g.in_idx[p];
+        const int hr = hubrank[u];
+        codes[h0 + j] = u == v ? HUB_SELF : hr > 0 ? -hr : g.lab[u];
+        mpos[h0 + j] = out ? bm.mir_o[p] : bm.mir_i[p];
     }
 }
+
 // End bytes from the labels, only when the mirrors could not be verified (the
 // sequential pass then leaves the bytes pointing at moved hubs stale).
 __global__ void __launch_bounds__(256) k_dense_ends_unmirrored(GDev g, DenseBM bm) {
@@ -1074,16 +1132,32 @@ __global__ void __launch_bounds__(256) k_dense_ends_unmirrored(GDev g, DenseBM b
 // Hybrid sweep, sequential part (Sec. II-B): the hubs order[0..nh) move one at
 // a time in that order, each evaluated against the state the previous ones
 // left and applied at once.  One workgroup keeps M, the block degrees and the
-// hubs' labels in LDS; a hub's neighbour blocks come from the labels (a hub
-// from LDS: its label may have changed in this pass); the proposal and the
-// scoring are those of the evaluation kernel (one lane per block, the corner,
-// degree and Hastings terms of r and s on lanes 0-11); an accepted move
-// updates M, the degrees and the label, and writes the new block into the
-// mirrors of the hub's edge ends.  At the end M, f(M) and the degrees go back
-// to global memory and the pass's totals to statistics slot `slot`.
-constexpr int HUBS_T = 1024;
+// hubs' labels in LDS.  A hub's neighbour blocks come from its precomputed
+// codes (a hub neighbour's block from LDS: it may have moved in this pass),
+// loaded one hub ahead so that the loads of the next hub overlap the scoring
+// of this one.  The proposal and the scoring are those of the evaluation
+// kernel (one lane per block; the corner, degree and Hastings terms of r and
+// s on lanes 0-11).  An accepted move updates M, the degrees and the label,
+// and writes the new block into the mirrors of the hub's edge ends.  At the
+// end M, f(M) and the degrees go back to global memory and the pass's totals
+// to statistics slot `slot`.
+constexpr int HUBS_T = 256;  // one wave per SIMD
+constexpr int HUB_PF = 4;    // ends per thread held one hub ahead (hub degree up to 1024)
+struct HubEnds {
+    int c[HUB_PF], m[HUB_PF];
+};
+__device__ __forceinline__ void hub_fetch(const int *__restrict__ codes, const int *__restrict__ mpos, int h0,
+                                          int k, int tid, HubEnds &e) {
+#pragma unroll
+    for (int q = 0; q < HUB_PF; ++q) {
+        const int j = tid + q * HUBS_T;
+        e.c[q] = j < k ? codes[h0 + j] : 0;
+        e.m[q] = j < k ? mpos[h0 + j] : -1;
+    }
+}
 __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const int *__restrict__ order, int nh,
-                                                       const int *__restrict__ hubrank,
+                                                       const int *__restrict__ kk, const int *__restrict__ hoff,
+                                                       const int *__restrict__ codes, const int *__restrict__ mpos,
                                                        long long *__restrict__ stats_part,
                                                        double *__restrict__ sum_part, int slot, SweepTraceDev tr) {
     __shared__ int Ms[DC * DC];
@@ -1091,12 +1165,26 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
     __shared__ unsigned H[DC];  // out | in << 16 ends of the hub into each block
     __shared__ int hl[SBP_HUBS_MAX];
     __shared__ int s_ell, s_t0, s_dec;
+    __shared__ uint64_t s_W[2][3];  // a hub's draw words 1-3 and first index, double-buffered by hub parity
+    __shared__ int s_j0[2];
     const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63;
     const double *tab = bm.ftab;
     const unsigned fmax = bm.ftab_max;
     const double eps = (double)g.eps, epsC = (double)g.eps * (double)C;
     const long long eC = (long long)g.eps * C;
     unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
+    const bool mirrored = bm.flags[0] == 1;
+    // wave 1 draws hub i's words while wave 0 scores hub i - 1
+    auto draw_hub = [&](int vv, int kvv, int slot_) {
+        const Words4 W = draw_words(g.seed, (uint32_t)vv, g.sweep, 0u, 0u);
+        const int kk_ = (kvv & 0xffff) + (kvv >> 16);
+        if (lane == 0) {
+            s_W[slot_][0] = W.w[1];
+            s_W[slot_][1] = W.w[2];
+            s_W[slot_][2] = W.w[3];
+            s_j0[slot_] = kk_ > 0 ? (int)draw_idx(W.w[0], (uint64_t)kk_) : -1;
+        }
+    };
     for (int i = tid; i < CC; i += HUBS_T) Ms[i] = bm.M[i];
     if (tid < C) {
         dos[tid] = bm.dout[tid];
@@ -1105,14 +1193,26 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
     for (int i = tid; i < nh; i += HUBS_T) hl[i] = g.lab[order[i]];
     long long n_prop = 0, n_self = 0, n_acc = 0;
     double s_dS = 0.0;
+    // hub i's meta and ends; hub i + 1's meta
+    int v = order[0], kv = kk[0], h0 = hoff[0];
+    HubEnds E;
+    hub_fetch(codes, mpos, h0, (kv & 0xffff) + (kv >> 16), tid, E);
+    // complete the first hub's loads here: a first use inside the loop would
+    // place the wait there, where it would also drain each next hub's loads
+#pragma unroll
+    for (int q = 0; q < HUB_PF; ++q) asm volatile("" ::"v"(E.c[q]), "v"(E.m[q]));
+    int v_n = nh > 1 ? order[1] : 0, kv_n = nh > 1 ? kk[1] : 0, h0_n = nh > 1 ? hoff[1] : 0;
+    if (tid >= 64 && tid < 128) draw_hub(v, kv, 0);
     __syncthreads();
     for (int i = 0; i < nh; ++i) {
-        const int v = order[i], r = hl[i];
-        const int op = g.out_ptr[v], kout = g.out_ptr[v + 1] - op;
-        const int ip = g.in_ptr[v], kin = g.in_ptr[v + 1] - ip;
-        const int k = kout + kin;
-        const Words4 W = draw_words(g.seed, (uint32_t)v, g.sweep, 0u, 0u);
-        const int j0 = k > 0 ? (int)draw_idx(W.w[0], (uint64_t)k) : -1;
+        const int r = hl[i];
+        const int kout = kv & 0xffff, kin = kv >> 16, k = kout + kin;
+        // the next hub's ends and the meta of the one after, in flight during this hub
+        HubEnds En;
+        hub_fetch(codes, mpos, h0_n, i + 1 < nh ? (kv_n & 0xffff) + (kv_n >> 16) : 0, tid, En);
+        const int v_nn = i + 2 < nh ? order[i + 2] : 0, kv_nn = i + 2 < nh ? kk[i + 2] : 0;
+        const int h0_nn = i + 2 < nh ? hoff[i + 2] : 0;
+        const int j0 = s_j0[i & 1];
         if (tid < C) H[tid] = 0;
         if (tid == 0) {
             s_ell = 0;
@@ -1120,22 +1220,42 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
         }
         __syncthreads();
         // neighbour blocks: a self-loop end counts in ell (its block is r)
-        for (int j = tid; j < k; j += HUBS_T) {
+#pragma unroll
+        for (int q = 0; q < HUB_PF; ++q) {
+            const int j = tid + q * HUBS_T;
+            if (j < k) {
+                const int c = E.c[q];
+                const bool out = j < kout;
+                int b = r;
+                if (c == HUB_SELF) {
+                    if (out) atomicAdd(&s_ell, 1);
+                } else {
+                    b = c >= 0 ? c : hl[-c - 1];
+                    atomicAdd(&H[b], out ? 1u : 65536u);
+                }
+                if (j == j0) s_t0 = b;
+            }
+        }
+        for (int j = tid + HUB_PF * HUBS_T; j < k; j += HUBS_T) {  // beyond the prefetched ends
+            const int c = codes[h0 + j];
             const bool out = j < kout;
-            const int u = out ? g.out_idx[op + j] : g.in_idx[ip + (j - kout)];
             int b = r;
-            if (u == v) {
+            if (c == HUB_SELF) {
                 if (out) atomicAdd(&s_ell, 1);
             } else {
-                const int hr = hubrank[u];
-                b = hr > 0 ? hl[hr - 1] : g.lab[u];
+                b = c >= 0 ? c : hl[-c - 1];
                 atomicAdd(&H[b], out ? 1u : 65536u);
             }
             if (j == j0) s_t0 = b;
         }
         __syncthreads();
+        if (tid >= 64 && tid < 128 && i + 1 < nh) draw_hub(v_n, kv_n, (i + 1) & 1);
         if (tid < 64) {
             const int t = lane;
+            Words4 W;
+            W.w[1] = s_W[i & 1][0];
+            W.w[2] = s_W[i & 1][1];
+            W.w[3] = s_W[i & 1][2];
             int s;
             if (k == 0) {
                 s = (int)draw_idx(W.w[2], (uint64_t)C);
@@ -1162,58 +1282,63 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
             double dS = 0.0, lnH = 0.0, z = 0.0;
             bool acc = false;
             if (act) {
+                // every lane issues its ten f lookups at once (one round trip):
+                // its block t's four changed entries before and after, and for
+                // lanes 0-7 one corner entry or block degree; an unused slot
+                // looks up f(0) - f(0), an exact zero
                 double dL = 0.0, qf = 0.0, qr = 0.0;
-                if (t < C && t != r && t != s) {
-                    const unsigned hv = H[t];
-                    const int ko = (int)(hv & 0xffffu), ki = (int)(hv >> 16);
-                    if (ko | ki) {
-                        const int Mrt = Ms[r * C + t], Mst = Ms[s * C + t], Mtr = Ms[t * C + r], Mts = Ms[t * C + s];
-                        if (ko) dL += fx(tab, fmax, Mrt - ko) - fx(tab, fmax, Mrt) + fx(tab, fmax, Mst + ko) - fx(tab, fmax, Mst);
-                        if (ki) dL += fx(tab, fmax, Mtr - ki) - fx(tab, fmax, Mtr) + fx(tab, fmax, Mts + ki) - fx(tab, fmax, Mts);
-                        const double kt = (double)(ko + ki), den = (double)(dos[t] + dis[t]) + epsC;
-                        qf += kt * (((double)(Mts + Mst) + eps) / den);
-                        qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+                const bool bt = t < C && t != r && t != s;
+                const int tc = bt ? t : 0;
+                const unsigned hv = bt ? H[tc] : 0u;
+                const int ko = (int)(hv & 0xffffu), ki = (int)(hv >> 16);
+                const int Mrt = Ms[r * C + tc], Mst = Ms[s * C + tc], Mtr = Ms[tc * C + r], Mts = Ms[tc * C + s];
+                const unsigned hr = H[r], hs = H[s];
+                const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
+                const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
+                const int ell = s_ell;
+                const int Mrr = Ms[r * C + r], Mrs = Ms[r * C + s], Msr = Ms[s * C + r], Mss = Ms[s * C + s];
+                const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
+                const int dor = dos[r], dos_ = dos[s], dir = dis[r], dis_ = dis[s];
+                int cx = 0, cy = 0;
+                switch (lane) {
+                    case 0: cx = Mrr + drr, cy = Mrr; break;
+                    case 1: cx = Mrs + drs, cy = Mrs; break;
+                    case 2: cx = Msr + dsr, cy = Msr; break;
+                    case 3: cx = Mss + dss, cy = Mss; break;
+                    case 4: cx = dor - kout, cy = dor; break;
+                    case 5: cx = dos_ + kout, cy = dos_; break;
+                    case 6: cx = dir - kin, cy = dir; break;
+                    case 7: cx = dis_ + kin, cy = dis_; break;
+                    default: break;
+                }
+                const double f0 = fx(tab, fmax, ko ? Mrt - ko : 0), g0 = fx(tab, fmax, ko ? Mrt : 0);
+                const double f1 = fx(tab, fmax, ko ? Mst + ko : 0), g1 = fx(tab, fmax, ko ? Mst : 0);
+                const double f2 = fx(tab, fmax, ki ? Mtr - ki : 0), g2 = fx(tab, fmax, ki ? Mtr : 0);
+                const double f3 = fx(tab, fmax, ki ? Mts + ki : 0), g3 = fx(tab, fmax, ki ? Mts : 0);
+                const double fc = fx(tab, fmax, cx), gc = fx(tab, fmax, cy);
+                // Hastings terms while the lookups are in flight
+                if (ko | ki) {
+                    const double kt = (double)(ko + ki), den = (double)(dos[tc] + dis[tc]) + epsC;
+                    qf += kt * (((double)(Mts + Mst) + eps) / den);
+                    qr += kt * (((double)(Mtr - ki + Mrt - ko) + eps) / den);
+                }
+                if (lane >= 8 && lane < 12) {  // t = r and t = s
+                    const double kd = (double)k;
+                    const double d_r = (double)dor + (double)dir, d_s = (double)dos_ + (double)dis_;
+                    int w, num;
+                    double den;
+                    switch (lane) {
+                        case 8: w = ko_r + ki_r + 2 * ell, num = Mrs + Msr, den = d_r + epsC; break;
+                        case 9: w = ko_s + ki_s, num = 2 * Mss, den = d_s + epsC; break;
+                        case 10: w = ko_r + ki_r, num = 2 * (Mrr + drr), den = d_r - kd + epsC; break;
+                        default: w = ko_s + ki_s + 2 * ell, num = Msr + dsr + Mrs + drs, den = d_s + kd + epsC; break;
+                    }
+                    if (w) {
+                        const double q = (double)w * (((double)num + eps) / den);
+                        if (lane < 10) qf += q; else qr += q;
                     }
                 }
-                if (lane < 12) {  // the blocks r and s themselves
-                    const unsigned hr = H[r], hs = H[s];
-                    const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
-                    const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
-                    const int ell = s_ell;
-                    const int Mrr = Ms[r * C + r], Mrs = Ms[r * C + s], Msr = Ms[s * C + r], Mss = Ms[s * C + s];
-                    const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s, dss = ko_s + ki_s + ell;
-                    const int dor = dos[r], dos_ = dos[s], dir = dis[r], dis_ = dis[s];
-                    if (lane < 8) {
-                        int x, y;
-                        switch (lane) {
-                            case 0: x = Mrr + drr, y = Mrr; break;
-                            case 1: x = Mrs + drs, y = Mrs; break;
-                            case 2: x = Msr + dsr, y = Msr; break;
-                            case 3: x = Mss + dss, y = Mss; break;
-                            case 4: x = dor - kout, y = dor; break;
-                            case 5: x = dos_ + kout, y = dos_; break;
-                            case 6: x = dir - kin, y = dir; break;
-                            default: x = dis_ + kin, y = dis_; break;
-                        }
-                        const double f = fx(tab, fmax, x) - fx(tab, fmax, y);
-                        dL += lane < 4 ? f : -f;
-                    } else {
-                        const double kd = (double)k;
-                        const double d_r = (double)dor + (double)dir, d_s = (double)dos_ + (double)dis_;
-                        int w, num;
-                        double den;
-                        switch (lane) {
-                            case 8: w = ko_r + ki_r + 2 * ell, num = Mrs + Msr, den = d_r + epsC; break;
-                            case 9: w = ko_s + ki_s, num = 2 * Mss, den = d_s + epsC; break;
-                            case 10: w = ko_r + ki_r, num = 2 * (Mrr + drr), den = d_r - kd + epsC; break;
-                            default: w = ko_s + ki_s + 2 * ell, num = Msr + dsr + Mrs + drs, den = d_s + kd + epsC; break;
-                        }
-                        if (w) {
-                            const double q = (double)w * (((double)num + eps) / den);
-                            if (lane < 10) qf += q; else qr += q;
-                        }
-                    }
-                }
+                dL = ((f0 - g0) + (f1 - g1)) + ((f2 - g2) + (f3 - g3)) + (lane < 4 ? fc - gc : gc - fc);
                 dL = wave_sum(dL);
                 qf = wave_sum(qf);
                 qr = wave_sum(qr);
@@ -1267,20 +1392,29 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
                 hl[i] = sd;
                 g.lab[v] = sd;
             }
-            if (bm.flags[0] == 1)  // the end bytes that point at v
-                for (int j = tid; j < k; j += HUBS_T) {
-                    if (j < kout) {
-                        const int p = op + j;
-                        const int q = bm.mir_o[p];
-                        if (g.out_idx[p] != v && (unsigned)q < (unsigned)g.e) nli[q] = (unsigned char)sd;
-                    } else {
-                        const int q = ip + (j - kout);
-                        const int p = bm.mir_i[q];
-                        if (g.in_idx[q] != v && (unsigned)p < (unsigned)g.e) nlo[p] = (unsigned char)sd;
-                    }
+            if (mirrored) {  // the end bytes that point at v: in-end bytes of out-ends, and the reverse
+#pragma unroll
+                for (int q = 0; q < HUB_PF; ++q) {
+                    const int j = tid + q * HUBS_T;
+                    const int m = E.m[q];
+                    if (j < k && E.c[q] != HUB_SELF && (unsigned)m < (unsigned)g.e)
+                        (j < kout ? nli : nlo)[m] = (unsigned char)sd;
                 }
+                for (int j = tid + HUB_PF * HUBS_T; j < k; j += HUBS_T) {
+                    const int m = mpos[h0 + j];
+                    if (codes[h0 + j] != HUB_SELF && (unsigned)m < (unsigned)g.e)
+                        (j < kout ? nli : nlo)[m] = (unsigned char)sd;
+                }
+            }
         }
         __syncthreads();
+        E = En;
+        v = v_n;
+        kv = kv_n;
+        h0 = h0_n;
+        v_n = v_nn;
+        kv_n = kv_nn;
+        h0_n = h0_nn;
     }
     for (int i = tid; i < CC; i += HUBS_T) {
         bm.M[i] = Ms[i];
@@ -1577,22 +1711,25 @@ int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *d
 }
 
 
-int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, uint64_t *k0, uint64_t *k1, void *temp,
-                   int *order, int *hubrank, const SweepTraceDev &tr, hipStream_t s) {
+int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, const HubScratch &h,
+                   const SweepTraceDev &tr, hipStream_t s) {
     if (n_hubs <= 0) return 0;
-    hipLaunchKernelGGL(k_hub_keys, dim3(grid_for(g.n, 256, 4096)), dim3(256), 0, s, g, k0, hubrank);
+    hipLaunchKernelGGL(k_hub_keys, dim3(grid_for(g.n, 256, 4096)), dim3(256), 0, s, g, h.k0, h.hubrank);
     SBP_LAUNCH_CHECK();
     int rc;
-    if ((rc = radix_sort(k0, k1, nullptr, nullptr, g.n, 48, temp, s))) return rc;
-    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n_hubs, 256, 64)), dim3(256), 0, s, (const uint64_t *)k0, n_hubs,
-                       order, hubrank);
-    hipLaunchKernelGGL(k_dense_hubs, dim3(1), dim3(HUBS_T), 0, s, g, bm, (const int *)order, n_hubs,
-                       (const int *)hubrank, ws.stats_part, ws.sum_part, ws.nwg, tr);
-    if (g.n > 0)
-        hipLaunchKernelGGL(k_dense_ends_unmirrored, dim3(grid_for((long long)g.n * 64, 256, 4096)), dim3(256), 0, s,
-                           g, bm);
+    // stable on the degree bits: ties keep the id order the keys were written in
+    if ((rc = radix_sort_bits(h.k0, h.k1, nullptr, nullptr, g.n, 32, 48, h.temp, s))) return rc;
+    hipLaunchKernelGGL(k_hub_mark, dim3(1), dim3(MARK_T), 0, s, g, (const uint64_t *)h.k0, n_hubs, h.order,
+                       h.hubrank, h.kk, h.hoff);
+    hipLaunchKernelGGL(k_hub_codes, dim3(n_hubs), dim3(256), 0, s, g, bm, (const int *)h.order, (const int *)h.kk,
+                       (const int *)h.hoff, (const int *)h.hubrank, h.codes, h.mpos);
+    hipLaunchKernelGGL(k_dense_hubs, dim3(1), dim3(HUBS_T), 0, s, g, bm, (const int *)h.order, n_hubs,
+                       (const int *)h.kk, (const int *)h.hoff, (const int *)h.codes, (const int *)h.mpos,
+                       ws.stats_part, ws.sum_part, ws.nwg, tr);
+    hipLaunchKernelGGL(k_dense_ends_unmirrored, dim3(grid_for((long long)g.n * 64, 256, 4096)), dim3(256), 0, s, g,
+                       bm);
     SBP_LAUNCH_CHECK();
-    ws.hubrank = hubrank;
+    ws.hubrank = h.hubrank;
     ws.hub_slot = ws.nwg;
     return 0;
 }

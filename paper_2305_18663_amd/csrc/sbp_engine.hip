@@ -1047,9 +1047,17 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         ds.stats_part = w.stats_part;
         ds.sum_part = w.sum_part;
         // hybrid schedule: the hubs one at a time, then the batches without them
-        if ((rc = dense_hub_pass(d, bv.d, ds, p->n_hubs, w.u.ws.k0, w.u.ws.k1, w.u.ws.temp, w.u.ws.i0, w.hub, tr,
-                                 s)))
-            return rc;
+        HubScratch hs{};
+        hs.k0 = w.u.ws.k0;
+        hs.k1 = w.u.ws.k1;
+        hs.temp = w.u.ws.temp;
+        hs.order = w.u.ws.i0;                   // [cap >= n]
+        hs.kk = w.u.ws.i1;                      // [cap >= n]
+        hs.hoff = (int *)w.u.ws.s0;             // [2 (cap + 1) >= n + 1]
+        hs.codes = (int *)w.u.ws.v0;            // [2 cap >= 2e]
+        hs.mpos = (int *)w.u.ws.v1;             // [2 cap >= 2e]
+        hs.hubrank = w.hub;                     // [n]
+        if ((rc = dense_hub_pass(d, bv.d, ds, p->n_hubs, hs, tr, s))) return rc;
         for (int b = 0; b < d.n_batches; ++b) {
             d.batch = b;
             if ((rc = dense_sweep_batch(d, bv.d, ds, tr, st, s))) return rc;

@@ -91,6 +91,9 @@ int scan_exclusive_i64(const long long *in, long long *out, long long n, long lo
 size_t radix_temp_bytes(long long n);
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *vals_alt, long long n, int bits,
                void *temp, hipStream_t s);
+// LSD passes over bits [lo, hi) only (stable, so equal digits keep their order).
+int radix_sort_bits(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *vals_alt, long long n, int lo,
+                    int hi, void *temp, hipStream_t s);
 int fill_i32(int *p, int value, long long n, hipStream_t s);
 int fill_i64(long long *p, long long value, long long n, hipStream_t s);
 int iota_i32(int *p, long long n, hipStream_t s);
@@ -187,8 +190,17 @@ struct DenseScratch {
 };
 // Hybrid sweep, sequential part, dense tier: the n_hubs vertices of highest
 // degree move one at a time (order, hubrank and the sort buffers are scratch).
-int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, uint64_t *k0, uint64_t *k1, void *temp,
-                   int *order, int *hubrank, const SweepTraceDev &tr, hipStream_t s);
+// Scratch of the sequential pass: sort keys [n] (k0, k1), radix temp, and
+// per hub (nh <= SBP_HUBS_MAX) the vertex, out | in << 16 end counts and end
+// offsets [nh + 1]; per hub edge end (at most 2e) a neighbour code and a
+// mirror position; hubrank [n].
+struct HubScratch {
+    uint64_t *k0, *k1;
+    void *temp;
+    int *order, *kk, *hoff, *codes, *mpos, *hubrank;
+};
+int dense_hub_pass(const GDev &g, DenseBM &bm, DenseScratch &ws, int n_hubs, const HubScratch &h,
+                   const SweepTraceDev &tr, hipStream_t s);
 constexpr int SBP_HUBS_MAX = 4096;
 int dense_build(const GDev &g, DenseBM &bm, int *delta, hipStream_t s);
 int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepTraceDev &tr,

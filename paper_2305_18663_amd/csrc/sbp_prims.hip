@@ -279,7 +279,12 @@ size_t radix_temp_bytes(long long n) {
 
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *vals_alt, long long n, int bits,
                void *temp, hipStream_t s) {
-    if (n <= 1 || bits <= 0) return 0;
+    return radix_sort_bits(keys, keys_alt, vals, vals_alt, n, 0, bits, temp, s);
+}
+
+int radix_sort_bits(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *vals_alt, long long n, int lo,
+                    int bits, void *temp, hipStream_t s) {
+    if (n <= 1 || bits <= lo) return 0;
     const long long ntiles = (n + RADIX_TILE - 1) / RADIX_TILE;
     const long long h = ntiles * RADIX_DIGITS;
     char *t = (char *)temp;
@@ -290,7 +295,7 @@ int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint64_t *vals, uint64_t *val
     void *stemp = t;
     uint64_t *ka = keys, *kb = keys_alt, *va = vals, *vb = vals_alt;
     int passes = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RADIX_BLOCK), 0, s, ka, n, shift, ntiles, hist);
         SBP_LAUNCH_CHECK();
         int rc = scan_exclusive_i32(hist, off, h, nullptr, stemp, s);

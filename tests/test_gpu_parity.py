@@ -311,6 +311,15 @@ def test_sweep_hybrid_chain():
         sbp.sbp_tune("dense_update_moved_share", 128)
 
 
+@pytest.mark.parametrize("n_batches", [1, 2])
+def test_sweep_hybrid_large_hubs(n_batches):
+    # five hubs of 505 to 15004 edge ends, three of them beyond the ends a
+    # thread of the sequential pass holds ahead, then the next-largest vertices
+    g = hub_graph()
+    lab0 = gen.initial_labels(g.n, 40, seed=40)
+    sweep_parity(g, lab0, 40, seed=43, sweep=2, n_batches=n_batches, n_hubs=12)
+
+
 def test_sweep_hybrid_200k():
     g = gen.sweep_200k()
     lab0 = gen.initial_labels(g.n, 45, seed=2001)
