@@ -48,8 +48,9 @@ def nmi(a, b) -> float:
     return float(normalized_mutual_info_score(a, b, average_method="arithmetic"))
 
 
-def run(names=None, seeds=(0,), scale=1.0, device="cuda:0", **partition_kw):
-    """Partition every (family, seed) graph in one batched launch; one row each."""
+def run(names=None, seeds=(0,), scale=1.0, device="cuda:0", keep_labels=False, **partition_kw):
+    """Partition every (family, seed) graph in one batched launch; one row each
+    (with the result labels under "lab" when keep_labels)."""
     import torch
 
     from . import sbp
@@ -73,6 +74,8 @@ def run(names=None, seeds=(0,), scale=1.0, device="cuda:0", **partition_kw):
         rows.append(dict(family=name, seed=s, n=g.n, e=g.e, planted=g.n_planted, C=r["C"], dl=r["dl"],
                          dl_norm=r["dl"] / dl_null(g.e), nmi=nmi(r["lab"], g.planted),
                          paper_nmi_1node=PAPER_NMI_1NODE.get(name)))
+        if keep_labels:
+            rows[-1]["lab"] = r["lab"]
     return rows, wall
 
 
