@@ -324,13 +324,16 @@ int sbp_engine_destroy(sbp_engine *eng);
  * Returns SBP_E_ARG for an unknown key or a value out of range. */
 int sbp_tune(const char *key, int64_t value);
 
-/* Kernel timing for measurement.  While enabled, HIP events are recorded
- * on the calling stream immediately before and after every launch of the
- * sweep-evaluation kernel ("sweep_eval"; dense and sparse tiers).
+/* Kernel timing for measurement.  on = 0 disables it; on = k >= 1 attaches
+ * HIP events to the start and end of every k-th launch of the
+ * sweep-evaluation kernel ("sweep_eval"; dense and sparse tiers), counting
+ * from the first launch after the call (k = 1: every launch).  Each pair of
+ * attached events costs the GPU a few microseconds, so a sampling stride
+ * k > 1 keeps a timed loop close to its unprofiled speed.
  * sbp_profile_read synchronises on those events and returns the summed
- * milliseconds and the number of launches since the last reset; reset = 1
- * clears the record.  Host-side bookkeeping only; returns SBP_E_ARG for an
- * unknown kernel name. */
+ * milliseconds and the number of timed launches since the last reset;
+ * reset = 1 clears the record.  Host-side bookkeeping only; returns
+ * SBP_E_ARG for on < 0 or an unknown kernel name. */
 int sbp_profile_enable(int32_t on);
 int sbp_profile_read(const char *kernel, double *ms /*[host]*/, int64_t *launches /*[host]*/, int32_t reset);
 

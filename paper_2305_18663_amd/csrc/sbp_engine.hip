@@ -37,15 +37,17 @@ int fail(int code, const std::string &msg) {
 
 // ---------------------------------------------------------------- kernel timing
 static std::mutex g_prof_mu;
-static bool g_prof_on = false;
+static int g_prof_stride = 0;  // 0: off; k: events on every k-th launch of each named kernel
 struct ProfRec {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    long long calls = 0;  // launches since profiling was enabled
 };
 static std::map<std::string, ProfRec> g_prof;
 
 ProfileScope::ProfileScope(const char *name, hipStream_t stream, bool attach) : s(stream), attach_(attach) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (g_prof_stride <= 0) return;
+    if (g_prof[name].calls++ % g_prof_stride != 0) return;  // not a sampled launch
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return;
     if (hipEventCreate(&b) != hipSuccess) {
@@ -1374,8 +1376,10 @@ int sbp_tune(const char *key, int64_t value) {
 }
 
 int sbp_profile_enable(int32_t on) {
+    if (on < 0) return fail(SBP_E_ARG, "profile stride must be >= 0");
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_on = on != 0;
+    g_prof_stride = on;
+    for (auto &kv : g_prof) kv.second.calls = 0;  // sampling starts at the next launch
     return 0;
 }
 

@@ -362,8 +362,9 @@ def sbp_tune(key, value):
     _check(lib().sbp_tune(key.encode(), int(value)))
 
 
-def sbp_profile_enable(on=True):
-    _check(lib().sbp_profile_enable(1 if on else 0))
+def sbp_profile_enable(on=True, stride=1):
+    """Time every `stride`-th sweep-evaluation launch with HIP events (off: on=False)."""
+    _check(lib().sbp_profile_enable(int(stride) if on else 0))
 
 
 def sbp_profile_read(kernel="sweep_eval", reset=True):

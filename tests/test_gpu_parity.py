@@ -518,3 +518,26 @@ def test_engine_continuous_admission():
     for i in range(len(graphs)):
         C, dl, lab = results[i]
         assert C == alone[i]["C"] and dl == alone[i]["dl"] and np.array_equal(lab, alone[i]["lab"])
+
+
+def test_profile_sampling_stride():
+    # events on every k-th evaluation launch from the enabling call on
+    g = GRAPHS["plain_1k"]()
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(gen.initial_labels(g.n, 10, seed=1))
+    bm = sbp.sbp_build_blockmodel(dg, lab, 10)
+    sbp.sbp_profile_read("sweep_eval", reset=True)
+    try:
+        for stride, want in ((3, 4), (1, 10), (11, 1)):
+            sbp.sbp_profile_enable(True, stride=stride)
+            for k in range(10):
+                sbp.sbp_nodal_sweep(dg, lab, 10, bm, 5, k, trace=False, stats=False)
+            ms, n = sbp.sbp_profile_read("sweep_eval", reset=True)
+            assert n == want and ms > 0.0
+        sbp.sbp_profile_enable(False)
+        sbp.sbp_nodal_sweep(dg, lab, 10, bm, 5, 10, trace=False, stats=False)
+        assert sbp.sbp_profile_read("sweep_eval", reset=True) == (0.0, 0)
+        with pytest.raises(sbp.SbpError):
+            sbp.sbp_profile_enable(True, stride=-2)
+    finally:
+        sbp.sbp_profile_enable(False)
