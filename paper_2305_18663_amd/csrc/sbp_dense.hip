@@ -137,21 +137,25 @@ __device__ void mirror_bytes(const GDev &g, const DenseBM &bm, const unsigned ch
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     unsigned char *nlo = bm.nl, *nli = bm.nl + bm.nl_in;
     const int v0 = (int)((long long)g.n * wg / nwg), v1 = (int)((long long)g.n * (wg + 1) / nwg);
+    const int elast = max(g.e - 1, 0);
     for (int tb = v0 + wv * 64; tb < v1; tb += nw * 64) {
         const int v = tb + lane;
         const unsigned x = v < v1 ? nb[v] : 0xffu;
+        // every moved lane's end ranges in one round trip
+        const int vc = min(v, g.n - 1);
+        const int lo0 = g.out_ptr[vc], lo1 = g.out_ptr[vc + 1], li0 = g.in_ptr[vc], li1 = g.in_ptr[vc + 1];
         for (uint64_t todo = __ballot(x != 0xffu); todo; todo &= todo - 1) {
             const int l = __builtin_ctzll(todo);
-            const int vv = tb + l;
             const unsigned char xn = (unsigned char)__shfl((int)x, l, 64);
-            const int o0 = g.out_ptr[vv], o1 = g.out_ptr[vv + 1], i0 = g.in_ptr[vv], i1 = g.in_ptr[vv + 1];
-            for (int p = o0 + lane; p < o1; p += 64) {
-                const int q = bm.mir_o[p];
-                if (nlo[p] != 0xffu && (unsigned)q < (unsigned)g.e) nli[q] = xn;
-            }
-            for (int q = i0 + lane; q < i1; q += 64) {
-                const int p = bm.mir_i[q];
-                if (nli[q] != 0xffu && (unsigned)p < (unsigned)g.e) nlo[p] = xn;
+            const int o0 = __shfl(lo0, l, 64), ko = __shfl(lo1, l, 64) - o0;
+            const int i0 = __shfl(li0, l, 64), ki = __shfl(li1, l, 64) - i0;
+            // out-end j and in-end j together, loads unconditional (positions clamped)
+            for (int j = lane; j < max(ko, ki); j += 64) {
+                const int p = min(o0 + j, elast), q = min(i0 + j, elast);
+                const int mq = bm.mir_o[p], mp = bm.mir_i[q];
+                const unsigned bo = nlo[p], bi = nli[q];
+                if (j < ko && bo != 0xffu && (unsigned)mq < (unsigned)g.e) nli[mq] = xn;
+                if (j < ki && bi != 0xffu && (unsigned)mp < (unsigned)g.e) nlo[mp] = xn;
             }
         }
     }
@@ -846,32 +850,42 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
         const int lane = tid & 63, wv = tid >> 6;
         const int v0 = (int)((long long)g.n * blockIdx.x / gridDim.x);
         const int v1 = (int)((long long)g.n * (blockIdx.x + 1) / gridDim.x);
+        const int elast = max(g.e - 1, 0);
         for (int tb = v0 + wv * 64; tb < v1; tb += UPD_T) {
             const int v = tb + lane;
             const unsigned x = v < v1 ? nb[v] : 0xffu;
+            // every moved lane's label and end ranges in one round trip
+            const int vc = min(v, g.n - 1);
+            const int la = g.lab[vc], lo0 = g.out_ptr[vc], lo1 = g.out_ptr[vc + 1];
+            const int li0 = g.in_ptr[vc], li1 = g.in_ptr[vc + 1];
             for (uint64_t todo = __ballot(x != 0xffu); todo; todo &= todo - 1) {
                 const int l = __builtin_ctzll(todo);
                 const int vv = tb + l;
                 const int xn = __shfl((int)x, l, 64);
-                const int a = g.lab[vv];
-                const int o0 = g.out_ptr[vv], o1 = g.out_ptr[vv + 1], i0 = g.in_ptr[vv], i1 = g.in_ptr[vv + 1];
-                for (int p = o0 + lane; p < o1; p += 64) {
-                    const unsigned b = nlo[p];
-                    if (b == 0xffu) {  // self-loop: (a, a) -> (x, x)
-                        atomicAdd(&dl[a * C + a], -1);
-                        atomicAdd(&dl[xn * C + xn], 1);
-                    } else {
-                        const unsigned xu = nb[g.out_idx[p]];
-                        const int bn = xu != 0xffu ? (int)xu : (int)b;
-                        atomicAdd(&dl[a * C + (int)b], -1);
-                        atomicAdd(&dl[xn * C + bn], 1);
+                const int a = __shfl(la, l, 64);
+                const int o0 = __shfl(lo0, l, 64), ko = __shfl(lo1, l, 64) - o0;
+                const int i0 = __shfl(li0, l, 64), ki = __shfl(li1, l, 64) - i0;
+                // out-end j and in-end j together; loads unconditional (positions
+                // clamped into the arrays), so both ends' reads overlap
+                for (int j = lane; j < max(ko, ki); j += 64) {
+                    const bool ho = j < ko, hi = j < ki;
+                    const int p = min(o0 + j, elast), q = min(i0 + j, elast);
+                    const unsigned bo = nlo[p], bi = nli[q];
+                    const unsigned xu = nb[g.out_idx[p]], xw = nb[g.in_idx[q]];
+                    if (ho) {
+                        if (bo == 0xffu) {  // self-loop: (a, a) -> (x, x)
+                            atomicAdd(&dl[a * C + a], -1);
+                            atomicAdd(&dl[xn * C + xn], 1);
+                        } else {
+                            const int bn = xu != 0xffu ? (int)xu : (int)bo;
+                            atomicAdd(&dl[a * C + (int)bo], -1);
+                            atomicAdd(&dl[xn * C + bn], 1);
+                        }
                     }
-                }
-                for (int q = i0 + lane; q < i1; q += 64) {
-                    const unsigned b = nli[q];
-                    if (b == 0xffu || nb[g.in_idx[q]] != 0xffu) continue;  // counted at the (moved) source
-                    atomicAdd(&dl[(int)b * C + a], -1);
-                    atomicAdd(&dl[(int)b * C + xn], 1);
+                    if (hi && bi != 0xffu && xw == 0xffu) {  // else counted at the (moved) source
+                        atomicAdd(&dl[(int)bi * C + a], -1);
+                        atomicAdd(&dl[(int)bi * C + xn], 1);
+                    }
                 }
                 if (lane == 0) g.lab[vv] = xn;
             }
