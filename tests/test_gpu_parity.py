@@ -320,6 +320,16 @@ def test_sweep_hybrid_large_hubs(n_batches):
     sweep_parity(g, lab0, 40, seed=43, sweep=2, n_batches=n_batches, n_hubs=12)
 
 
+def test_sweep_hybrid_edge_cases():
+    # hubs without edges (the uniform proposal), one block (every proposal is
+    # the own block), every vertex a hub on a mostly isolated graph
+    g = gen.from_edges(50, [0, 1, 2, 3, 3], [1, 2, 3, 0, 3])  # 46 isolated, a self-loop
+    for C, n_hubs in ((1, 5), (2, 50), (7, 50), (49, 50)):
+        lab0 = gen.initial_labels(g.n, C, seed=C)
+        sweep_parity(g, lab0, C, seed=3, sweep=C, n_hubs=n_hubs)
+        sweep_parity(g, lab0, C, seed=3, sweep=C, n_batches=4, n_hubs=n_hubs)
+
+
 def test_sweep_hybrid_200k():
     g = gen.sweep_200k()
     lab0 = gen.initial_labels(g.n, 45, seed=2001)
