@@ -1280,11 +1280,11 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
                     s = (int)draw_idx(W.w[2], (uint64_t)C);
                 } else {
                     // the first block whose running sum of e_t0,b = M_t0,b + M_b,t0 exceeds x
-                    const long long x = (long long)draw_idx(W.w[2], (uint64_t)dt);
-                    long long e = t < C ? (long long)Ms[t0 * C + t] + Ms[t * C + t0] : 0;
+                    const int x = (int)draw_idx(W.w[2], (uint64_t)dt);  // dt <= 2e < 2^31
+                    int e = t < C ? Ms[t0 * C + t] + Ms[t * C + t0] : 0;
 #pragma unroll
                     for (int o = 1; o < 64; o <<= 1) {
-                        const long long y = __shfl_up(e, o, 64);
+                        const int y = __shfl_up(e, o, 64);
                         if (lane >= o) e += y;
                     }
                     const uint64_t hit = __ballot(t < C && e > x);
@@ -1353,9 +1353,12 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
                     }
                 }
                 dL = ((f0 - g0) + (f1 - g1)) + ((f2 - g2) + (f3 - g3)) + (lane < 4 ? fc - gc : gc - fc);
-                dL = wave_sum(dL);
-                qf = wave_sum(qf);
-                qr = wave_sum(qr);
+                dL = grp_sum<32>(dL);
+                qf = grp_sum<32>(qf);
+                qr = grp_sum<32>(qr);
+                dL += __shfl_xor(dL, 32, 64);
+                qf += __shfl_xor(qf, 32, 64);
+                qr += __shfl_xor(qr, 32, 64);
                 dS = -dL;
                 lnH = k > 0 ? log(qr) - log(qf) : 0.0;
                 z = -g.beta * dS + lnH;
