@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-TIMING_STRIDE = 10  # evaluation launches per HIP-event-timed launch in the timed loop
+TIMED_LAUNCHES = 5  # evaluation launches timed with HIP events in the timed loop (evenly spaced)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_eval_traffic.json")
 EVAL_SOURCE = os.path.join(ROOT, "paper_2305_18663_amd", "csrc", "sbp_dense.hip")
 
@@ -54,22 +54,62 @@ def eval_bytes_per_sweep(g):
     return 16 * g.n + 8 * (2 * g.e)
 
 
+def host_cpu():
+    """CPU model, logical CPUs and the cores this process may run on."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = sorted(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = list(range(os.cpu_count() or 1))
+    return model, os.cpu_count() or 1, allowed
+
+
+class pinned_to_one_core:
+    """Runs the enclosed code with this process pinned to one allowed core."""
+
+    def __enter__(self):
+        self.core = None
+        try:
+            self.saved = os.sched_getaffinity(0)
+            self.core = max(self.saved)
+            os.sched_setaffinity(0, {self.core})
+        except (AttributeError, OSError):
+            self.saved = None
+        return self
+
+    def __exit__(self, *exc):
+        if self.saved is not None:
+            os.sched_setaffinity(0, self.saved)
+
+
 def cpu_baseline(g, lab0, C, seed, budget_s=15.0, max_sweeps=4):
+    """The oracle (single-threaded FP64 C, gcc -O2) on the first sweeps of the
+    same workload, pinned to one core of the host."""
     from oracle import oracle as O
     O.build()
+    model, nproc, allowed = host_cpu()
     lab = lab0.copy()
-    t0 = time.perf_counter()
-    done = 0
-    while done < max_sweeps:
-        r = O.nodal_sweep(g, lab, C, seed, done)
-        lab = r["lab"]
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    with pinned_to_one_core() as pin:
+        t0 = time.perf_counter()
+        done = 0
+        while done < max_sweeps:
+            r = O.nodal_sweep(g, lab, C, seed, done)
+            lab = r["lab"]
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
     return {"value": g.n * done / dt, "unit": "vertex proposals/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} sweeps of the same 200k-vertex workload, single-threaded FP64 C oracle "
-                      f"(gcc -O2) on {platform.processor() or platform.machine()}, {dt:.1f} s"}
+                      f"(gcc -O2), {dt:.1f} s",
+            "cpu_model": model, "nproc": nproc, "allowed_cores": len(allowed), "pinned_core": pin.core}
 
 
 def _batch_member(args):
@@ -175,6 +215,74 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def _oracle_partition_child(q, which, seed):
+    from oracle import oracle as O
+    from paper_2305_18663_amd import gen
+    with pinned_to_one_core():
+        g = gen.plain_1k() if which == "partition1k" else gen.sweep_200k()
+        t0 = time.perf_counter()
+        r = O.partition(g, seed=seed)
+        q.put((time.perf_counter() - t0, int(r["C"]), float(r["dl"]), r["lab"]))
+
+
+def bench_partition(args):
+    """The whole method (merges, MCMC, golden search) from C = N on one graph:
+    the 1k-vertex, 10-block workload or the 200k-vertex sweep workload, beside
+    the oracle run in a child process on one core (a bounded leg: reported as
+    not finished when it exceeds its budget)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_2305_18663_amd import gen, sbp
+    which = args.workload
+    seed = 2000 if which == "partition1k" else 2001
+    budget = args.oracle_budget
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    child = ctx.Process(target=_oracle_partition_child, args=(q, which, seed), daemon=True)
+    child.start()  # before any GPU use in this process
+    g = gen.plain_1k() if which == "partition1k" else gen.sweep_200k()
+    torch.cuda.set_device(0)
+    dg = sbp.DeviceGraph(g, "cuda:0")
+    sbp.sbp_partition(dg, seed=seed, max_iters=2)  # warm-up (library load, first launches)
+    torch.cuda.synchronize()
+    times, res = [], None
+    for _ in range(args.repeats):
+        t0 = time.perf_counter()
+        res = sbp.sbp_partition(dg, seed=seed)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    progress(f"{which}: GPU partition {min(times):.3f} s, C={res['C']}")
+    oracle = {"kind": "oracle", "cores": 1, "budget_s": budget}
+    try:
+        t_o, C_o, dl_o, lab_o = q.get(timeout=budget)
+        oracle.update(time_s=t_o, C=C_o, dl=dl_o, identical=bool(C_o == res["C"] and np.array_equal(lab_o, res["lab"])))
+    except Exception:
+        oracle.update(time_s=None, finished=False)
+    if child.is_alive():
+        child.terminate()
+    child.join()
+    model, nproc, _ = host_cpu()
+    oracle.update(cpu_model=model, nproc=nproc)
+    sweeps = int(res["trace"][:, 3].sum()) if len(res["trace"]) else 0
+    line = {"metric": "whole-method partition time (from C = N)", "value": min(times), "unit": "s",
+            "n_gpus": 1, "steps": args.repeats, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": ("directed DCSBM N=1000, 10 equal blocks, E=8000, ratio 2.5, PL(2.1,[1,100])"
+                                    if which == "partition1k" else
+                                    "directed DCSBM N=200000, 45 blocks (sizes spread 5x), E=4000000, ratio 2.5"),
+                       "vertices": g.n, "edges": g.e, "seed": seed},
+            "times_s": times, "C": res["C"], "dl": res["dl"], "iterations": len(res["trace"]), "sweeps": sweeps,
+            "dl_norm": res["dl"] / ((g.e + 1) * np.log(g.e + 1)),
+            "cpu_baseline": oracle}
+    if which == "partition1k":
+        from sklearn.metrics import normalized_mutual_info_score
+        line["nmi"] = float(normalized_mutual_info_score(res["lab"], g.planted, average_method="arithmetic"))
+    print(json.dumps(line), flush=True)
+
+
 def bench_sparse1m(args):
     """The 1M-vertex, 180-block sparse workload: merge scoring at C = N (the
     first merge phase), sweeps on the sparse tier at C = 500000 from a seeded
@@ -253,10 +361,14 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sweep", "batch", "serve", "sparse1m"], default="sweep")
+    ap.add_argument("--workload", choices=["sweep", "batch", "serve", "sparse1m", "partition1k", "partition200k"],
+                    default="sweep")
+    ap.add_argument("--repeats", type=int, default=3, help="partition workloads: timed runs")
+    ap.add_argument("--oracle-budget", type=float, default=120.0,
+                    help="partition workloads: seconds the oracle leg may take before it is reported unfinished")
     ap.add_argument("--graphs", type=int, default=256)
     ap.add_argument("--skip-partition", action="store_true", help="sparse1m: merges and sweeps only")
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--calibration", type=int, default=100)
     ap.add_argument("--hubs", type=int, default=0,
                     help="sweep workload: the highest-degree vertices moved one at a time first (hybrid sweep)")
@@ -273,6 +385,8 @@ def main():
         return bench_sparse1m(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload in ("partition1k", "partition200k"):
+        return bench_partition(args)
 
     import numpy as np
     import torch
@@ -305,9 +419,11 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     sbp.sbp_profile_read("sweep_eval", reset=True)
-    # HIP events on every TIMING_STRIDE-th evaluation launch of the timed
-    # loop: attaching them to every launch would slow each sweep by ~5 us
-    sbp.sbp_profile_enable(True, stride=TIMING_STRIDE)
+    # HIP events on TIMED_LAUNCHES evenly spaced evaluation launches of the
+    # timed loop: attaching them to every launch would slow each sweep by a
+    # few microseconds
+    stride = max(1, args.steps // TIMED_LAUNCHES)
+    sbp.sbp_profile_enable(True, stride=stride)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
@@ -324,6 +440,7 @@ def main():
     avg_eval_s = eval_ms / max(launches, 1) / 1e3
     bytes_launch = eval_bytes_per_sweep(g)
     achieved = bytes_launch / avg_eval_s / 1e9
+    traffic = measured_traffic()
     line = {
         "metric": "vertex proposals/s (200k-vertex sweep)",
         "value": value,
@@ -342,10 +459,13 @@ def main():
                    "vertices": g.n, "edges": g.e, "blocks": C, "batches_per_sweep": 1, "hubs_per_sweep": args.hubs, "beta": 3.0, "eps": 1,
                    "dl_after": dl},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_dense_eval", "avg_launch_us": avg_eval_s * 1e6,
-                     "timed_launches": launches, "timing_stride": TIMING_STRIDE,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "timed_launches": launches, "timing_stride": stride,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     # the counters' bytes over the same launch time: what the HBM actually moved
+                     "traffic_gbs": traffic / avg_eval_s / 1e9 if traffic else None,
+                     "traffic_frac": traffic / avg_eval_s / 1e9 / HBM_PEAK_GBS if traffic else None},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, lab0, C, seed)

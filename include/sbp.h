@@ -256,15 +256,18 @@ int sbp_compact(int32_t n, int32_t *assign, int32_t C, int32_t *C_new /*[host]*/
 /* ------------------------------------------------------------------ */
 /* Agglomerative SBP: start from assign_in (labels < C_in, compacted) or,
  * when assign_in is NULL, from every vertex in its own block; alternate a
- * merge phase (Alg. 1) and an MCMC phase (Alg. 2, stopped when
- * |DL_prev - DL| < t DL or after max_sweeps sweeps, then compacted) while a
- * golden-ratio search over C keeps three (C, DL, assignment) results:
- * before a bracket exists the next target is C_mid - floor(C_mid merge_rate)
- * from the best result; afterwards the larger of the segments
- * (C_hi - C_mid) and (C_mid - C_lo) is split at 0.382 (upper, from the hi
- * result) or 0.618 (lower, from the best result).  Stops when
+ * merge phase (Alg. 1) down to a target count and an MCMC phase (Alg. 2,
+ * stopped when |DL_prev - DL| < t DL or after max_sweeps sweeps) at that
+ * count, while a golden-ratio search over C keeps three (C, DL, assignment)
+ * results, each stored at the count its merge phase produced (blocks the
+ * MCMC phase emptied stay as empty labels and count in C of Eq. 2): before a
+ * bracket exists the next target is C_mid - floor(C_mid merge_rate) from the
+ * best result; afterwards the larger of the segments (C_hi - C_mid) and
+ * (C_mid - C_lo) is split 0.382 of its length away from mid (upper: merged
+ * down from the hi result; lower: from the best result).  Stops when
  * C_hi - C_lo <= 2 (C_mid - C_lo <= 1 without hi), when no merge is
- * possible, or after max_iters iterations; returns the best result.
+ * possible, or after max_iters iterations; returns the best result with
+ * its empty labels dropped (C_out non-empty blocks) and its DL at C_out.
  * Merge phase k uses phase index k; sweeps are numbered across the run.
  * Workspace: sbp_partition_workspace_bytes.  SYNC. */
 size_t sbp_partition_workspace_bytes(int32_t n_graphs, const int32_t *n /*[host]*/, const int32_t *e /*[host]*/);
@@ -280,9 +283,10 @@ int sbp_partition_batch(int32_t n_graphs, const sbp_graph *graphs /*[host]*/,
                         int32_t *C_out /*[host]*/, double *dl_out /*[host]*/,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* Per-iteration record of the last sbp_partition / finished engine graph
- * (host): rows of [C_start, C_target, C_after_merge, sweeps, C_final] and
- * the DL of each result.  Returns the number of rows written. */
+/* Per-iteration record of a finished graph (host): rows of [C_start,
+ * C_target, C_after_merge, sweeps, C_stored] and the DL of each stored
+ * result.  `tag` is the engine tag (-1 for sbp_partition).  The record is
+ * removed once read.  Returns the number of rows written (0 if none). */
 int sbp_partition_trace(int64_t tag, int64_t *rows /*[host] 5*cap*/, double *dl /*[host] cap*/, int32_t cap);
 
 /* Continuous batching engine.  Graphs are admitted while their footprint

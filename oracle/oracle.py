@@ -70,7 +70,10 @@ def lib():
                                        ct.c_int, ct.c_int64, I32P, F64P, F64P]
         L.orc_merge_delta.argtypes = [ct.c_int, I32P, I32P, I32P, ct.c_int, ct.c_int, ct.c_int,
                                       ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
+        L.orc_merge_propose.argtypes = [ct.c_int, I32P, I32P, I32P, ct.c_int, ct.c_int, U64P, ct.c_int64]
         L.orc_merge_apply.argtypes = [ct.c_int, I32P, F64P, ct.c_int, I32P]
+        L.orc_golden_insert.argtypes = [I32P, F64P, I32P, ct.c_int, ct.c_double, ct.POINTER(ct.c_int)]
+        L.orc_golden_next.argtypes = [I32P, I32P, ct.c_double, ct.POINTER(ct.c_int)]
         L.orc_compact.argtypes = [ct.c_int, I32P, ct.c_int]
         L.orc_partition.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, ct.c_void_p, ct.c_int,
                                     ct.POINTER(_Params), I32P, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double),
@@ -171,6 +174,14 @@ def merge_delta(g, lab, C, c, cp):
     return dS.value, dSl.value
 
 
+def merge_propose(g, lab, C, c, W, eps=1):
+    """The partner one set of words W0..W3 proposes for block c (Alg. 1 proposal step; may be c)."""
+    cp = lib().orc_merge_propose(g.n, g.out_ptr, g.out_idx, _i32(lab), C, c, np.asarray(W, np.uint64), eps)
+    if cp < 0:
+        raise ValueError("bad merge proposal arguments")
+    return cp
+
+
 def merge_apply(partner, dS_local, n_merges):
     C = len(partner)
     m = np.zeros(max(C, 1), np.int32)
@@ -182,6 +193,31 @@ def compact(lab, C):
     lab = _i32(lab).copy()
     c = lib().orc_compact(len(lab), lab, C)
     return c, lab
+
+
+# ---------------------------------------------------------------- golden-ratio search (Sec. II-B)
+class Golden:
+    """The (hi, mid, lo) triple of the oracle's golden-ratio search over C."""
+
+    def __init__(self):
+        self.C = np.zeros(3, np.int32)
+        self.dl = np.zeros(3)
+        self.used = np.zeros(3, np.int32)
+
+    def insert(self, C, dl):
+        """Stores a result; returns (slot written, slot the old mid moved to or -1)."""
+        moved = ct.c_int(-1)
+        to = lib().orc_golden_insert(self.C, self.dl, self.used, C, dl, ct.byref(moved))
+        return to, moved.value
+
+    def next(self, merge_rate=0.5):
+        """(start slot, target C), or None when the search is over."""
+        t = ct.c_int(0)
+        frm = lib().orc_golden_next(self.C, self.used, merge_rate, ct.byref(t))
+        return None if frm < 0 else (frm, t.value)
+
+    def slots(self):
+        return [(int(self.C[k]), float(self.dl[k])) if self.used[k] else None for k in range(3)]
 
 
 # ---------------------------------------------------------------- whole method

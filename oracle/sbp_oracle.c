@@ -608,6 +608,34 @@ static double merge_delta_L(const obm *m, int c, int cp)
     return dL;
 }
 
+/* One merge proposal for block c from the words W (Alg. 1, "propose a new
+ * community c' to merge with c"; the law is a reading, the paper gives none):
+ * with d_c = 0 a uniform block among the C-1 others, idx(W2, C-1) skipping c;
+ * otherwise t is the block of a random edge end of c, drawn from e_c. with
+ * idx(W0, d_c); then a uniform block among the C-1 others when
+ * idx(W1, d_t + eps C) < eps C, else a block drawn from e_t. with idx(W2, d_t).
+ * The result may be c itself (an invalid proposal). */
+static int merge_propose(const obm *m, int c, const uint64_t W[4], int64_t eps)
+{
+    const int C = m->C;
+    int64_t dc = m->dout[c] + m->din[c];
+    if (dc == 0) {
+        int64_t kk = draw_index(W[2], (uint64_t)(C - 1));
+        return (int)(kk + (kk >= c));
+    }
+    int t = neighbour_block_draw(m, c, draw_index(W[0], (uint64_t)dc));
+    int64_t dt = m->dout[t] + m->din[t];
+    if (draw_index(W[1], (uint64_t)(dt + eps * C)) < eps * C) {
+        int64_t kk = draw_index(W[2], (uint64_t)(C - 1));
+        return (int)(kk + (kk >= c));
+    }
+    return neighbour_block_draw(m, t, draw_index(W[2], (uint64_t)dt));
+}
+
+/* The x proposals of every block (words from counter (c, phase, 2j|2j+1, 1)
+ * for j < x).  A proposal of c itself is invalid and still counts toward x.
+ * The valid candidate with the smallest floor(dS_local 2^20) is kept, the
+ * first on ties; without one, partner = -1 and dS = +inf. */
 static void merge_scores_on(const obm *m, uint64_t seed, uint32_t phase, int x, int64_t eps,
                             int *partner, double *dS, double *dS_local)
 {
@@ -619,21 +647,7 @@ static void merge_scores_on(const obm *m, uint64_t seed, uint32_t phase, int x, 
         for (int j = 0; j < x && C > 1; ++j) {
             uint64_t W[4];
             orc_words(seed, (uint32_t)c, phase, (uint32_t)(2 * j), 1, W);
-            int cp;
-            int64_t dc = m->dout[c] + m->din[c];
-            if (dc == 0) {
-                int64_t kk = draw_index(W[2], (uint64_t)(C - 1));
-                cp = (int)(kk + (kk >= c));
-            } else {
-                int t = neighbour_block_draw(m, c, draw_index(W[0], (uint64_t)dc));
-                int64_t dt = m->dout[t] + m->din[t];
-                if (draw_index(W[1], (uint64_t)(dt + eps * C)) < eps * C) {
-                    int64_t kk = draw_index(W[2], (uint64_t)(C - 1));
-                    cp = (int)(kk + (kk >= c));
-                } else {
-                    cp = neighbour_block_draw(m, t, draw_index(W[2], (uint64_t)dt));
-                }
-            }
+            int cp = merge_propose(m, c, W, eps);
             if (cp == c) continue;
             double local = -merge_delta_L(m, c, cp);
             if (rank_key(local) < rank_key(best_local)) { best = cp; best_local = local; }
@@ -642,6 +656,18 @@ static void merge_scores_on(const obm *m, uint64_t seed, uint32_t phase, int x, 
         dS_local[c] = best < 0 ? INFINITY : best_local;
         dS[c] = best < 0 ? INFINITY : best_local + offset;
     }
+}
+
+/* Exported: the partner block one set of words proposes for c (may be c). */
+int orc_merge_propose(int n, const int *out_ptr, const int *out_idx, const int *lab, int C, int c,
+                      const uint64_t W[4], int64_t eps)
+{
+    if (c < 0 || c >= C || C < 2) return -1;
+    obm m;
+    if (obm_build(&m, n, out_ptr, out_idx, lab, C)) return -1;
+    int cp = merge_propose(&m, c, W, eps);
+    obm_free(&m);
+    return cp;
 }
 
 /* Exported: full DL change and its local part for merging c and cp. */
@@ -739,8 +765,76 @@ static int compact_labels(int n, int *lab, int C)
 int orc_compact(int n, int *lab, int C) { return compact_labels(n, lab, C); }
 
 /* ------------------------------------------------------------------ */
+/* Golden-ratio search over the block count (Sec. II-B; the steps after */
+/* the bracket exists are a reading: integer golden-section search).    */
+/* Slots 0 = hi, 1 = mid, 2 = lo hold (C, DL) with C_hi > C_mid > C_lo  */
+/* and DL_mid the least stored DL.                                      */
+/* ------------------------------------------------------------------ */
+/* Inserts result (Cr, dlr).  A result better than mid becomes mid and
+ * the old mid moves to hi when Cr < C_mid, else to lo; a result that is not
+ * better replaces lo when Cr < C_mid, else hi.  The first result becomes
+ * mid.  Returns the slot written; *displaced (nullable) receives the slot
+ * the old mid moved to, or -1. */
+int orc_golden_insert(int C[3], double dl[3], int used[3], int Cr, double dlr, int *displaced)
+{
+    int to = 1, moved = -1;
+    if (!used[1]) {
+        to = 1;
+    } else if (dlr < dl[1]) {
+        moved = Cr < C[1] ? 0 : 2;
+        C[moved] = C[1]; dl[moved] = dl[1]; used[moved] = 1;
+        to = 1;
+    } else {
+        to = Cr < C[1] ? 2 : 0;
+    }
+    C[to] = Cr; dl[to] = dlr; used[to] = 1;
+    if (displaced) *displaced = moved;
+    return to;
+}
+
+/* Next block count to try.  Before a bracket exists (no lo): halve from mid,
+ * target C_mid - floor(C_mid merge_rate) (Alg. 1, "until the number of
+ * communities is halved").  With a bracket, the larger of the segments
+ * (C_hi - C_mid) and (C_mid - C_lo) is split 0.382 of its length away from
+ * mid: upper: C_mid + max(1, round(0.381966 (C_hi - C_mid))), below C_hi,
+ * merged down from hi; lower: C_lo + max(1, round(0.618034 (C_mid - C_lo))),
+ * below C_mid, merged down from mid.  Returns the start slot (0 or 1) and
+ * writes *target, or returns -1 when the search is over: C_hi - C_lo <= 2,
+ * C_mid - C_lo <= 1 without hi, or no merge left before the bracket. */
+int orc_golden_next(const int C[3], const int used[3], double merge_rate, int *target)
+{
+    if (!used[2]) {
+        int merges = (int)floor(C[1] * merge_rate);
+        if (merges < 1) return -1;
+        *target = C[1] - merges;
+        return 1;
+    }
+    int upper = used[0] ? C[0] - C[1] : 0;
+    int lower = C[1] - C[2];
+    if (used[0] ? (C[0] - C[2] <= 2) : (lower <= 1)) return -1;
+    if (used[0] && upper >= lower) {
+        int step = (int)floor(0.381966 * upper + 0.5);
+        if (step < 1) step = 1;
+        int t = C[1] + step;
+        *target = t > C[0] - 1 ? C[0] - 1 : t;
+        return 0;
+    }
+    int step = (int)floor(0.618034 * lower + 0.5);
+    if (step < 1) step = 1;
+    int t = C[2] + step;
+    *target = t > C[1] - 1 ? C[1] - 1 : t;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
 /* Whole method (Sec. II-B): agglomerative alternation of block merges  */
 /* and MCMC, with the golden-ratio search over the block count.         */
+/* An iteration merges the start assignment down to the target count    */
+/* (Alg. 1), runs the MCMC phase at that count (Alg. 2; blocks it        */
+/* empties stay as empty labels, so C in Eq. 2 is the count the merge   */
+/* phase produced) and stores (C, DL, assignment) in the golden triple.  */
+/* The returned assignment is the best stored one with its empty labels */
+/* dropped, and its DL is recomputed at the non-empty count.            */
 /* ------------------------------------------------------------------ */
 typedef struct {
     uint64_t seed;
@@ -754,9 +848,30 @@ typedef struct {
     int max_iters;
 } opart_params;
 
-typedef struct { int C; double dl; int *lab; int used; } oslot;
+/* One MCMC phase (Alg. 2 outer loop) at C blocks: sweeps until
+ * |DL_prev - DL| < t DL after a sweep, or max_sweeps sweeps; the sweep index
+ * in the random-number counter continues from *sweep_ctr.  Returns the
+ * number of sweeps and writes the final DL. */
+static int mcmc_phase(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx,
+                      int *lab, int C, const opart_params *p, double tol, uint32_t *sweep_ctr, double *dl_out)
+{
+    double dl_prev = orc_description_length(n, out_ptr, out_idx, lab, C);
+    double dl = dl_prev;
+    int sweeps = 0;
+    while (sweeps < p->max_sweeps) {
+        orc_nodal_sweep(n, out_ptr, out_idx, in_ptr, in_idx, lab, C, p->seed, (*sweep_ctr)++, p->beta, p->eps,
+                        p->n_batches, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
+        ++sweeps;
+        dl = orc_description_length(n, out_ptr, out_idx, lab, C);
+        int stop = fabs(dl_prev - dl) < tol * dl;
+        dl_prev = dl;
+        if (stop) break;
+    }
+    *dl_out = dl;
+    return sweeps;
+}
 
-/* trace row per iteration: [C_start, C_target, C_merged, sweeps, C_final] as int64, and DL */
+/* trace row per iteration: [C_start, C_target, C_merged, sweeps, C_stored] as int64, and DL */
 int orc_partition(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx,
                   const int *lab_in, int C_in, const opart_params *p,
                   int *lab_out, int *C_out, double *dl_out,
@@ -775,17 +890,21 @@ int orc_partition(int n, const int *out_ptr, const int *out_idx, const int *in_p
         for (int v = 0; v < n; ++v) lab[v] = v;
         C = n;
     }
-    oslot hi = {0, 0, NULL, 0}, mid = {0, 0, NULL, 0}, lo = {0, 0, NULL, 0};
+    /* golden triple: counts, DLs and assignments of slots hi, mid, lo */
+    int gC[3] = {0, 0, 0}, gused[3] = {0, 0, 0};
+    double gdl[3] = {0, 0, 0};
+    int *glab[3];
+    for (int k = 0; k < 3; ++k) glab[k] = (int *)malloc(sizeof(int) * (size_t)n);
     uint32_t sweep_ctr = 0, phase_ctr = 0;
     int iters = 0;
 
-    /* insert a result into the (hi, mid, lo) golden triple */
-#define SLOT_SET(S, CC, DL, LAB) do { if (!(S).lab) (S).lab = (int *)malloc(sizeof(int) * (size_t)n); \
-        memcpy((S).lab, (LAB), sizeof(int) * (size_t)n); (S).C = (CC); (S).dl = (DL); (S).used = 1; } while (0)
-#define SLOT_MOVE(DST, SRC) do { oslot tmp_ = (DST); (DST) = (SRC); (SRC) = tmp_; } while (0)
+    /* store the assignment in lab as the result (Cr, dlr) */
+#define GOLDEN_STORE(CR, DLR) do { int from_ = -1; \
+        int to_ = orc_golden_insert(gC, gdl, gused, (CR), (DLR), &from_); \
+        if (from_ >= 0) { int *t_ = glab[from_]; glab[from_] = glab[1]; glab[1] = t_; } \
+        memcpy(glab[to_], lab, sizeof(int) * (size_t)n); } while (0)
 
-    double dl0 = orc_description_length(n, out_ptr, out_idx, lab, C);
-    SLOT_SET(mid, C, dl0, lab);
+    GOLDEN_STORE(C, orc_description_length(n, out_ptr, out_idx, lab, C));
 
     int *map = (int *)malloc(sizeof(int) * (size_t)n);
     int *partner = (int *)malloc(sizeof(int) * (size_t)n);
@@ -793,34 +912,11 @@ int orc_partition(int n, const int *out_ptr, const int *out_idx, const int *in_p
     double *dSl = (double *)malloc(sizeof(double) * (size_t)n);
 
     while (iters < p->max_iters) {
-        /* next block count to try (golden-ratio search, Sec. II-B) */
-        const oslot *start;
         int target;
-        if (!lo.used) {
-            int merges = (int)floor(mid.C * p->merge_rate);
-            if (merges < 1) break;
-            start = &mid;
-            target = mid.C - merges;
-        } else {
-            int upper = hi.used ? hi.C - mid.C : 0;
-            int lower = mid.C - lo.C;
-            if (hi.used ? (hi.C - lo.C <= 2) : (lower <= 1)) break;
-            if (hi.used && upper >= lower) {
-                int step = (int)floor(0.381966 * upper + 0.5);
-                if (step < 1) step = 1;
-                target = mid.C + step;
-                if (target > hi.C - 1) target = hi.C - 1;
-                start = &hi;
-            } else {
-                int step = (int)floor(0.618034 * lower + 0.5);
-                if (step < 1) step = 1;
-                target = lo.C + step;
-                if (target > mid.C - 1) target = mid.C - 1;
-                start = &mid;
-            }
-        }
-        int C0 = start->C;
-        memcpy(lab, start->lab, sizeof(int) * (size_t)n);
+        int from = orc_golden_next(gC, gused, p->merge_rate, &target);
+        if (from < 0) break;
+        int C0 = gC[from];
+        memcpy(lab, glab[from], sizeof(int) * (size_t)n);
 
         /* block merge phase (Alg. 1) */
         orc_merge_scores(n, out_ptr, out_idx, lab, C0, p->seed, phase_ctr++, p->merge_proposals, p->eps,
@@ -828,43 +924,26 @@ int orc_partition(int n, const int *out_ptr, const int *out_idx, const int *in_p
         int C1 = orc_merge_apply(C0, partner, dSl, C0 - target, map);
         for (int v = 0; v < n; ++v) lab[v] = map[lab[v]];
 
-        /* MCMC phase (Alg. 2): sweeps until |DL_prev - DL| < t DL or max_sweeps */
-        double tol = lo.used ? p->t_post : p->t_pre;
-        double dl_prev = orc_description_length(n, out_ptr, out_idx, lab, C1);
-        int sweeps = 0;
-        while (sweeps < p->max_sweeps) {
-            orc_nodal_sweep(n, out_ptr, out_idx, in_ptr, in_idx, lab, C1, p->seed, sweep_ctr++, p->beta, p->eps,
-                            p->n_batches, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
-            ++sweeps;
-            double dl = orc_description_length(n, out_ptr, out_idx, lab, C1);
-            int stop = fabs(dl_prev - dl) < tol * dl;
-            dl_prev = dl;
-            if (stop) break;
-        }
-        int C2 = compact_labels(n, lab, C1);
-        double dlR = orc_description_length(n, out_ptr, out_idx, lab, C2);
+        /* MCMC phase (Alg. 2) at C1 blocks */
+        double dlR;
+        int sweeps = mcmc_phase(n, out_ptr, out_idx, in_ptr, in_idx, lab, C1, p,
+                                gused[2] ? p->t_post : p->t_pre, &sweep_ctr, &dlR);
         if (trace && iters < trace_cap) {
             trace[5 * iters + 0] = C0; trace[5 * iters + 1] = target; trace[5 * iters + 2] = C1;
-            trace[5 * iters + 3] = sweeps; trace[5 * iters + 4] = C2;
+            trace[5 * iters + 3] = sweeps; trace[5 * iters + 4] = C1;
             if (trace_dl) trace_dl[iters] = dlR;
         }
         ++iters;
-
-        /* insert R into the triple */
-        if (dlR < mid.dl) {
-            if (C2 < mid.C) { SLOT_MOVE(hi, mid); } else { SLOT_MOVE(lo, mid); }
-            SLOT_SET(mid, C2, dlR, lab);
-        } else {
-            if (C2 < mid.C) { SLOT_SET(lo, C2, dlR, lab); } else { SLOT_SET(hi, C2, dlR, lab); }
-        }
+        GOLDEN_STORE(C1, dlR);
     }
-#undef SLOT_SET
-#undef SLOT_MOVE
-    memcpy(lab_out, mid.lab, sizeof(int) * (size_t)n);
-    *C_out = mid.C;
-    *dl_out = mid.dl;
+#undef GOLDEN_STORE
+    /* the best result without its empty labels */
+    memcpy(lab_out, glab[1], sizeof(int) * (size_t)n);
+    int Cf = compact_labels(n, lab_out, gC[1]);
+    *C_out = Cf;
+    *dl_out = orc_description_length(n, out_ptr, out_idx, lab_out, Cf);
     if (n_iters) *n_iters = iters;
-    free(hi.lab); free(mid.lab); free(lo.lab);
+    for (int k = 0; k < 3; ++k) free(glab[k]);
     free(lab); free(map); free(partner); free(dS); free(dSl);
     return 0;
 }

@@ -529,7 +529,7 @@ struct GraphRun {
     size_t pool_off = 0, pool_bytes = 0;
     int eslot = 0;  // engine slot (index into Cdev)
     int C = 0;
-    enum Phase { START, LOAD, PRE_MERGE, MERGED, MCMC, COMPACTED, DONE } phase = START;
+    enum Phase { START, LOAD, PRE_MERGE, MERGED, MCMC, FINAL, DONE } phase = START;
     int action = ACT_NONE;
     int merges = 0;
     int C0 = 0, target = 0, C1 = 0, sweeps = 0, iters = 0, batch = 0;
@@ -650,11 +650,22 @@ int golden_next(GraphRun &r, int &target) {
     return 1;
 }
 
-void finish(sbp_engine *eng, GraphRun &r) {
-    r.phase = GraphRun::DONE;
-    r.final_C = r.slotC[1];
-    r.final_dl = r.slotDL[1];
+// The search is over: the best stored assignment is loaded and compacted on
+// the next step; the step after that reads its non-empty count and DL.
+void start_final(sbp_engine *eng, GraphRun &r) {
+    r.phase = GraphRun::FINAL;
+    r.C = r.slotC[1];
+    r.action = ACT_COMPACT;
     (void)hipMemcpyAsync(r.lab, r.slot_lab[1], (size_t)r.g.n * 4, hipMemcpyDeviceToDevice, eng->s);
+}
+
+// Trace row of the finished iteration and the result into the golden triple.
+void store_result(sbp_engine *eng, GraphRun &r, double dl) {
+    r.trace.insert(r.trace.end(), {(long long)r.C0, (long long)r.target, (long long)r.C1, (long long)r.sweeps,
+                                   (long long)r.C1});
+    r.trace_dl.push_back(dl);
+    ++r.iters;
+    golden_insert(r, r.C1, dl, eng->s);
 }
 
 // Advance one graph after its DL and block count were read back.
@@ -665,7 +676,7 @@ void advance(sbp_engine *eng, GraphRun &r, double dl, int C) {
         int target = 0;
         const int from = golden_next(r, target);
         if (from < 0) {
-            finish(eng, r);
+            start_final(eng, r);
             return;
         }
         r.C0 = r.slotC[from];
@@ -693,8 +704,8 @@ void advance(sbp_engine *eng, GraphRun &r, double dl, int C) {
         r.sweeps = 0;
         r.batch = 0;
         if (r.p.max_sweeps < 1) {
-            r.action = ACT_COMPACT;
-            r.phase = GraphRun::COMPACTED;
+            store_result(eng, r, dl);
+            plan_next();
         } else {
             r.action = ACT_SWEEP;
             r.phase = GraphRun::MCMC;
@@ -712,21 +723,20 @@ void advance(sbp_engine *eng, GraphRun &r, double dl, int C) {
         const bool stop = std::fabs(r.dl_prev - dl) < r.tol * dl || r.sweeps >= r.p.max_sweeps;
         r.dl_prev = dl;
         if (stop) {
-            r.action = ACT_COMPACT;
-            r.phase = GraphRun::COMPACTED;
+            // the result is stored at the merged count: blocks the MCMC phase
+            // emptied stay as empty labels
+            store_result(eng, r, dl);
+            plan_next();
         } else {
             r.batch = 0;
             r.action = ACT_SWEEP;
         }
         break;
     }
-    case GraphRun::COMPACTED:
-        r.trace.insert(r.trace.end(), {(long long)r.C0, (long long)r.target, (long long)r.C1, (long long)r.sweeps,
-                                       (long long)C});
-        r.trace_dl.push_back(dl);
-        ++r.iters;
-        golden_insert(r, C, dl, eng->s);
-        plan_next();
+    case GraphRun::FINAL:
+        r.phase = GraphRun::DONE;
+        r.final_C = C;
+        r.final_dl = dl;
         break;
     default:
         break;
@@ -1418,6 +1428,7 @@ int sbp_partition_trace(int64_t tag, int64_t *rows, double *dl, int32_t cap) {
         for (int j = 0; j < 5; ++j) rows[5 * i + j] = tr.first[5 * i + j];
         dl[i] = tr.second[i];
     }
+    g_traces.erase(it);  // read once: a long-lived server does not keep every finished graph's record
     return k;
 }
 

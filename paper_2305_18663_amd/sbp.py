@@ -420,7 +420,8 @@ class Engine:
         while lib().sbp_engine_poll(self.h, ct.byref(tag), ct.byref(C), ct.byref(dl)):
             out = self.outputs.pop(tag.value)
             self.graphs.pop(tag.value, None)
-            done.append((tag.value, C.value, dl.value, out))
+            trace, _ = sbp_partition_trace(tag.value)  # read (and so released) with the result
+            done.append((tag.value, C.value, dl.value, out, trace))
         return done
 
     def close(self):

@@ -35,6 +35,8 @@ class Request:
     C: int = 0
     dl: float = 0.0
     labels: np.ndarray | None = None
+    error: str | None = None   # set when the request can never be served (it is not run)
+    trace: np.ndarray | None = None
 
 
 def graph_bytes(n: int, e: int) -> int:
@@ -52,25 +54,44 @@ class PartitionServer:
         self.budget = int(hbm_budget) - self.engine_bytes
         if self.budget <= 0:
             raise ValueError("HBM budget smaller than the engine workspace")
+        self.max_vertices, self.max_edges, self.max_graphs = int(max_vertices), int(max_edges), int(max_graphs)
         self.in_use = 0
+        self.used_v = self.used_e = 0
         self.resident = {}
+        self.staged = {}  # tag -> DeviceGraph uploaded for an admission that has not succeeded yet
+
+    def never_fits(self, req: Request) -> str | None:
+        """Why the request cannot be served even by an empty engine, or None."""
+        g = req.graph
+        if g.n > self.max_vertices:
+            return f"{g.n} vertices exceed the engine's {self.max_vertices}"
+        if g.e > self.max_edges:
+            return f"{g.e} edges exceed the engine's {self.max_edges}"
+        if graph_bytes(g.n, g.e) > self.budget:
+            return "graph larger than the HBM budget"
+        return None
 
     def _try_admit(self, req: Request, now: float) -> bool:
         g = req.graph
         need = graph_bytes(g.n, g.e)
-        if self.in_use + need > self.budget:
+        # host-side checks first, so a request that does not fit now is not uploaded
+        if (self.in_use + need > self.budget or self.used_v + g.n > self.max_vertices or
+                self.used_e + g.e > self.max_edges or len(self.resident) >= self.max_graphs):
             return False
-        dg = sbp.DeviceGraph(g, self.device)
+        dg = self.staged.pop(req.tag, None) or sbp.DeviceGraph(g, self.device)
         if not self.engine.admit(dg, req.tag, **req.params):
-            del dg
+            self.staged[req.tag] = dg  # kept for the next attempt (engine pool fragmentation)
             return False
         self.in_use += need
+        self.used_v += g.n
+        self.used_e += g.e
         self.resident[req.tag] = (dg, need)
         req.admitted = now
         return True
 
     def run(self, requests: list[Request], clock=time.perf_counter):
-        """Serve the requests at their arrival times; returns them completed."""
+        """Serve the requests at their arrival times; returns them completed.
+        A request that can never fit is answered at once with `error` set."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         by_tag = {r.tag: r for r in requests}
         active = 0
@@ -78,7 +99,16 @@ class PartitionServer:
         while pending or active:
             now = clock() - t0
             # admit in arrival order while the head fits
-            while pending and pending[0].arrival <= now and self._try_admit(pending[0], now):
+            while pending and pending[0].arrival <= now:
+                head = pending[0]
+                why = self.never_fits(head)
+                if why is not None:
+                    head.error = why
+                    head.admitted = head.done = now
+                    pending.popleft()
+                    continue
+                if not self._try_admit(head, now):
+                    break
                 pending.popleft()
                 active += 1
             if active == 0:
@@ -86,13 +116,16 @@ class PartitionServer:
                     time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
                 continue
             self.engine.step()
-            for tag, C, dl, out in self.engine.poll():
+            for tag, C, dl, out, trace in self.engine.poll():
                 r = by_tag[tag]
                 r.done = clock() - t0
                 r.C, r.dl = C, dl
                 r.labels = out.cpu().numpy()
+                r.trace = trace
                 dg, need = self.resident.pop(tag)
                 self.in_use -= need
+                self.used_v -= r.graph.n
+                self.used_e -= r.graph.e
                 active -= 1
         return requests
 
@@ -118,7 +151,9 @@ def serve_sequential(requests: list[Request], device="cuda", clock=time.perf_cou
 
 
 def latency_summary(requests: list[Request]) -> dict:
-    lat = np.array([r.done - r.arrival for r in requests])
-    makespan = max(r.done for r in requests) - min(r.arrival for r in requests)
+    served = [r for r in requests if r.error is None]
+    lat = np.array([r.done - r.arrival for r in served])
+    makespan = max(r.done for r in served) - min(r.arrival for r in served)
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "graphs_per_s": len(requests) / makespan, "makespan_s": makespan}
+            "mean_s": float(lat.mean()), "graphs_per_s": len(served) / makespan, "makespan_s": makespan,
+            "rejected": len(requests) - len(served)}

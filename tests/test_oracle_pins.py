@@ -389,6 +389,256 @@ def test_merge_delta_equals_full_recompute(gi):
                 assert a[0] == pytest.approx(b[0], rel=1e-12, abs=1e-9)
 
 
+def merge_graphs():
+    """(graph, labels, C) cases for the merge proposal law: self-loops (e_tt = 2 M_tt),
+    an empty label (d_c = 0) and blocks of very different degree."""
+    g1 = gen.random_multigraph(9, 25, seed=7, self_loops=True)
+    lab1 = np.array([0, 1, 2, 0, 1, 2, 0, 1, 2], np.int32)  # label 3 is empty
+    g2 = gen.dcsbm([3, 3], 14, 2.0, seed=21, kmax=4)
+    lab2 = gen.initial_labels(g2.n, 3, seed=5)
+    return [(g1, lab1, 4), (g2, lab2, 3)]
+
+
+def enumerate_merge_proposals(g, lab, C, c, eps):
+    """Exact law of the partner the oracle proposes for block c: every index
+    the three words can take, weighed by its probability (exact fractions).
+    The branch structure assumed here is the written reading of Alg. 1's
+    proposal step; the oracle is only called, never consulted for it."""
+    from fractions import Fraction
+    M = dense_M(g, lab, C)
+    e = M + M.T
+    d = M.sum(0) + M.sum(1)
+    prob = {}
+    if d[c] == 0:
+        for x2 in range(C - 1):
+            cp = O.merge_propose(g, lab, C, c, [0, 0, word_for(x2, C - 1), 0], eps)
+            prob[cp] = prob.get(cp, 0) + Fraction(1, C - 1)
+        return prob
+    cum = np.cumsum(e[c])
+    for x0 in range(int(d[c])):
+        t = int(np.argmax(cum > x0))  # ascending CDF over e_c.
+        n1 = int(d[t]) + eps * C
+        for x1 in range(n1):
+            n2 = C - 1 if x1 < eps * C else int(d[t])
+            for x2 in range(n2):
+                W = [word_for(x0, int(d[c])), word_for(x1, n1), word_for(x2, n2), 0]
+                cp = O.merge_propose(g, lab, C, c, W, eps)
+                prob[cp] = prob.get(cp, 0) + Fraction(1, int(d[c]) * n1 * n2)
+    return prob
+
+
+def closed_form_merge_q(g, lab, C, c, cp, eps):
+    """P(c -> c') = sum_t (e_ct/d_c) [eps C/(d_t + eps C) [c' != c]/(C-1) + e_tc'/(d_t + eps C)],
+    with e = M + M^T; a block without edges proposes uniformly among the others."""
+    from fractions import Fraction
+    M = dense_M(g, lab, C)
+    e = M + M.T
+    d = M.sum(0) + M.sum(1)
+    if d[c] == 0:
+        return Fraction(int(cp != c), C - 1)
+    q = Fraction(0)
+    for t in range(C):
+        if e[c, t] == 0:
+            continue
+        den = int(d[t]) + eps * C
+        q += Fraction(int(e[c, t]), int(d[c])) * (Fraction(eps * C * int(cp != c), den * (C - 1)) +
+                                                  Fraction(int(e[t, cp]), den))
+    return q
+
+
+@pytest.mark.parametrize("case", range(2))
+@pytest.mark.parametrize("eps", [1, 2])
+def test_merge_proposal_law_exact_enumeration(case, eps):
+    g, lab, C = merge_graphs()[case]
+    for c in range(C):
+        prob = enumerate_merge_proposals(g, lab, C, c, eps)
+        assert sum(prob.values()) == 1
+        for cp in range(C):
+            assert prob.get(cp, 0) == closed_form_merge_q(g, lab, C, c, cp, eps), (c, cp)
+    if case == 0:  # the empty label proposes every other block with equal weight
+        from fractions import Fraction
+        assert enumerate_merge_proposals(g, lab, C, 3, eps) == {k: Fraction(1, 3) for k in range(3)}
+
+
+@pytest.mark.parametrize("case", range(2))
+def test_merge_scores_keep_best_of_x_draws(case):
+    # partner = the best valid candidate among the x proposals drawn from
+    # counters (c, phase, 2j, 1), j < x: a proposal of c itself is skipped and
+    # is not replaced by another draw; the first of equal keys wins
+    g, lab, C = merge_graphs()[case]
+    seed, phase, x = 99, 3, 4
+    partner, dS, dSl = O.merge_scores(g, lab, C, seed, phase, x=x)
+    invalid = 0
+    for c in range(C):
+        best, best_key, best_local = -1, None, None
+        for j in range(x):
+            cp = O.merge_propose(g, lab, C, c, O.words(seed, c, phase, 2 * j, 1))
+            if cp == c:
+                invalid += 1
+                continue
+            local = O.merge_delta(g, lab, C, c, cp)[1]
+            key = math.floor(local * 2 ** 20)
+            if best_key is None or key < best_key:
+                best, best_key, best_local = cp, key, local
+        assert partner[c] == best
+        if best >= 0:
+            assert dSl[c] == best_local
+        else:
+            assert dS[c] == np.inf
+    if case == 0:
+        assert invalid > 0  # the seed exercises invalid draws
+
+
+def test_merge_all_draws_invalid():
+    # block 0 has only internal edges: with eps = 0 every proposal is block 0
+    # itself, so all x draws are invalid and block 0 gets no partner
+    g = gen.from_edges(6, [0, 1, 2, 3, 4, 5, 3], [1, 2, 0, 4, 5, 3, 5])
+    lab = np.array([0, 0, 0, 1, 1, 1], np.int32)
+    partner, dS, dSl = O.merge_scores(g, lab, 2, seed=5, phase=0, x=10, eps=0)
+    assert partner[0] == -1 and dS[0] == np.inf and dSl[0] == np.inf
+    assert partner[1] == -1
+    partner, dS, dSl = O.merge_scores(g, lab, 2, seed=5, phase=0, x=10, eps=1)
+    assert partner[0] == 1 and partner[1] == 0
+
+
+# ---------------------------------------------------------------- golden-ratio search over C (Sec. II-B)
+def test_golden_search_hand_worked():
+    # A scripted sequence of (C, DL) results, each expected step worked out by
+    # hand from the golden-section rules: halve until a bracket exists, then
+    # split the larger segment 0.382 of its length away from mid (upper: from
+    # hi; lower: from mid), stop when hi - lo <= 2.
+    gs = O.Golden()
+    assert gs.insert(100, 1000.0) == (1, -1)
+    assert gs.next() == (1, 50)                    # no bracket: 100 - floor(100/2)
+    assert gs.insert(50, 900.0) == (1, 0)          # better and smaller: old mid -> hi
+    assert gs.slots() == [(100, 1000.0), (50, 900.0), None]
+    assert gs.next() == (1, 25)                    # still no lo: halve from mid
+    assert gs.insert(25, 950.0) == (2, -1)         # worse and smaller -> lo
+    assert gs.next() == (0, 69)                    # upper 50 >= lower 25: 50 + round(19.10) from hi
+    assert gs.insert(69, 880.0) == (1, 2)          # better and larger: old mid -> lo
+    assert gs.slots() == [(100, 1000.0), (69, 880.0), (50, 900.0)]
+    assert gs.next() == (0, 81)                    # upper 31 >= lower 19: 69 + round(11.84)
+    assert gs.insert(81, 890.0) == (0, -1)         # worse and larger -> hi
+    assert gs.next() == (1, 62)                    # upper 12 < lower 19: 50 + round(11.74) from mid
+    assert gs.insert(62, 885.0) == (2, -1)
+    assert gs.next() == (0, 74)                    # upper 12 >= lower 7: 69 + round(4.58)
+    assert gs.insert(74, 870.0) == (1, 2)
+    assert gs.next() == (0, 77)                    # upper 7 >= lower 5: 74 + round(2.67)
+    assert gs.insert(77, 875.0) == (0, -1)
+    assert gs.next() == (1, 72)                    # upper 3 < lower 5: 69 + round(3.09)
+    assert gs.insert(72, 872.0) == (2, -1)
+    assert gs.next() == (0, 75)                    # upper 3 >= lower 2: 74 + max(1, round(1.15))
+    assert gs.insert(75, 871.0) == (0, -1)
+    assert gs.next() == (1, 73)                    # upper 1 < lower 2: 72 + round(1.24)
+    assert gs.insert(73, 869.0) == (1, 0)          # better and smaller: old mid -> hi
+    assert gs.slots() == [(74, 870.0), (73, 869.0), (72, 872.0)]
+    assert gs.next() is None                       # hi - lo = 2: done
+
+
+def test_golden_search_stop_rules():
+    # no merge left before a bracket: C_mid = 1
+    gs = O.Golden()
+    gs.insert(1, 10.0)
+    assert gs.next() is None
+    # merge_rate sets the first halving
+    gs = O.Golden()
+    gs.insert(40, 10.0)
+    assert gs.next(merge_rate=0.25) == (1, 30)
+    # bracket without hi (the start was never beaten): stop once C_mid - C_lo <= 1
+    gs = O.Golden()
+    gs.insert(3, 10.0)
+    assert gs.next() == (1, 2)
+    gs.insert(2, 11.0)
+    assert gs.slots() == [None, (3, 10.0), (2, 11.0)]
+    assert gs.next() is None
+    # bracket without hi but a wider lower segment: split it from mid
+    gs = O.Golden()
+    gs.insert(9, 10.0)
+    gs.insert(4, 12.0)
+    assert gs.next() == (1, 7)                     # 4 + round(0.618 * 5)
+    # hi - lo = 3 still splits; an equal DL is not better (the stored mid stays)
+    gs = O.Golden()
+    for C, dl in ((10, 5.0), (8, 4.0), (7, 4.5)):
+        gs.insert(C, dl)
+    assert gs.slots() == [(10, 5.0), (8, 4.0), (7, 4.5)]
+    assert gs.next() == (0, 9)                     # upper 2 >= lower 1
+    assert gs.insert(9, 4.0) == (0, -1)
+    assert gs.next() is None
+
+
+def _composed_partition(g, max_iters, **kw):
+    """The whole method composed in the test from the oracle's pinned pieces:
+    the golden triple, merge scoring and application (Alg. 1), sweeps until
+    |DL_prev - DL| < t DL (Alg. 2 stop rule) at the merged count, and the best
+    result compacted at the end."""
+    p = dict(O.DEFAULTS)
+    p.update(kw)
+    n = g.n
+    lab = np.arange(n, dtype=np.int32)
+    gs = O.Golden()
+    store = {}
+
+    def keep(C, dl, lab):
+        to, moved = gs.insert(C, dl)
+        if moved >= 0:
+            store[moved] = store[1]
+        store[to] = lab.copy()
+
+    keep(n, O.description_length(g, lab, n), lab)
+    sweep, phase, trace = 0, 0, []
+    while len(trace) < max_iters:
+        nxt = gs.next(p["merge_rate"])
+        if nxt is None:
+            break
+        frm, target = nxt
+        C0 = int(gs.C[frm])
+        lab = store[frm].copy()
+        partner, dS, dSl = O.merge_scores(g, lab, C0, p["seed"], phase, x=p["merge_proposals"], eps=p["eps"])
+        phase += 1
+        C1, m = O.merge_apply(partner, dSl, C0 - target)
+        lab = m[lab]
+        tol = p["t_post"] if gs.used[2] else p["t_pre"]
+        dl_prev = O.description_length(g, lab, C1)
+        sweeps = 0
+        while sweeps < p["max_sweeps"]:
+            lab = O.nodal_sweep(g, lab, C1, p["seed"], sweep, beta=p["beta"], eps=p["eps"])["lab"]
+            sweep += 1
+            sweeps += 1
+            dl = O.description_length(g, lab, C1)
+            stop = abs(dl_prev - dl) < tol * dl
+            dl_prev = dl
+            if stop:
+                break
+        trace.append((C0, target, C1, sweeps, C1, dl))
+        keep(C1, dl, lab)
+    C, lab = O.compact(store[1], int(gs.C[1]))
+    return lab, C, O.description_length(g, lab, C), trace
+
+
+@pytest.mark.parametrize("kw", [dict(t_pre=5e-4, t_post=1e-4), dict(t_pre=1e-2, t_post=3e-3, max_sweeps=6),
+                                dict(t_pre=0.0, t_post=0.0, max_sweeps=3)])
+def test_partition_equals_composition_of_pinned_steps(kw):
+    g = gen.dcsbm([40] * 5, 1600, 4.0, seed=77, kmax=20)
+    lab, C, dl, trace = _composed_partition(g, 200, seed=5, **kw)
+    res = O.partition(g, seed=5, **kw)
+    assert res["C"] == C and np.array_equal(res["lab"], lab) and res["dl"] == dl
+    assert len(trace) == len(res["trace"])
+    for row, ref in zip(res["trace"], trace):
+        assert tuple(int(x) for x in row) == ref[:5]
+    assert np.array_equal(res["trace_dl"], np.array([t[5] for t in trace]))
+    if kw["t_pre"] == 0.0:  # no DL change is below a zero tolerance: every phase runs max_sweeps
+        assert all(t[3] == 3 for t in trace)
+
+
+def test_partition_stops_golden_search():
+    # the search ends by its own rule well before the iteration cap
+    g = gen.dcsbm([40] * 5, 1600, 4.0, seed=77, kmax=20)
+    res = O.partition(g, seed=5)
+    assert len(res["trace"]) < 40
+    Cs = [int(r[4]) for r in res["trace"]]
+    assert len(set(Cs)) == len(Cs)  # every stored count is new
+
+
 def test_merge_scores_singletons_1k():
     g = gen.plain_1k()
     lab = np.arange(g.n, dtype=np.int32)
