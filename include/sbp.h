@@ -218,6 +218,23 @@ int sbp_nodal_sweep(const sbp_graph *g /*[host]*/, int32_t *assign, int32_t C, v
                     const sbp_sweep_params *p /*[host]*/, sbp_sweep_stats *stats,
                     const sbp_sweep_trace *trace /*[host]*/, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of sbp_nodal_sweep, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * semantics and results as sbp_nodal_sweep without ws/ws_bytes; its
+ * scratch (the per-vertex decisions and per-workgroup partials) is a
+ * file-scope device array of the library, about 4.2 MB on every GPU it runs
+ * on, held until the process ends.  Limits: dense tier only (C <=
+ * SBP_DENSE_MAX_C, else SBP_E_ARG), n_hubs = 0 (else SBP_E_ARG), n <=
+ * SBP_STATIC_MAX_VERTICES (else SBP_E_LIMIT); every check happens before any
+ * work is enqueued.  It calls no allocating routine.  All calls on one GPU
+ * share the array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+#define SBP_STATIC_MAX_VERTICES (1 << 20)
+int sbp_nodal_sweep_static(const sbp_graph *g /*[host]*/, int32_t *assign, int32_t C, void *bm, size_t bm_bytes,
+                           const sbp_sweep_params *p /*[host]*/, sbp_sweep_stats *stats,
+                           const sbp_sweep_trace *trace /*[host]*/, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Block merges (Alg. 1)                                               */
 /* ------------------------------------------------------------------ */

@@ -496,6 +496,105 @@ SingleWS single_layout(void *base, size_t cap, int n, int e) {
     return w;
 }
 
+int check_sweep_args(const sbp_graph *g, const int32_t *assign, int32_t C, const void *bm,
+                     const sbp_sweep_params *p) {
+    int rc;
+    if ((rc = check_graph_args(g))) return rc;
+    if (!assign || !bm || !p || C < 1 || C > g->n || p->n_batches < 1 || p->eps < 0 || !(p->beta > 0))
+        return fail(SBP_E_ARG, "bad sweep arguments");
+    if (p->n_hubs < 0 || p->n_hubs > std::min(g->n, SBP_HUBS_MAX))
+        return fail(SBP_E_ARG, "n_hubs must lie in [0, min(n, 4096)]");
+    return 0;
+}
+
+SweepTraceDev trace_of(const sbp_sweep_trace *trace) {
+    SweepTraceDev tr{};
+    if (trace) {
+        tr.prop = trace->prop;
+        tr.dS = trace->dS;
+        tr.lnH = trace->lnH;
+        tr.margin = trace->margin;
+        tr.accept = trace->accept;
+    }
+    return tr;
+}
+
+GDev sweep_desc(const sbp_graph *g, int32_t *assign, int32_t C, const sbp_sweep_params *p) {
+    GDev d = gdev_of(g, assign, C);
+    d.seed = p->seed;
+    d.sweep = p->sweep;
+    d.beta = p->beta;
+    d.eps = p->eps;
+    d.n_batches = std::min(p->n_batches, g->n);
+    d.action = ACT_SWEEP;
+    return d;
+}
+
+// One sweep on the dense tier: the optional sequential hub pass, then the
+// batches (the first batch starts the totals in st).
+int dense_sweep(GDev d, BMView &bv, DenseScratch &ds, int n_hubs, const HubScratch &hs, const SweepTraceDev &tr,
+                sbp_sweep_stats_dev *st, hipStream_t s) {
+    int rc;
+    ds.delta = bv.delta;
+    if ((rc = dense_hub_pass(d, bv.d, ds, n_hubs, hs, tr, s))) return rc;
+    for (int b = 0; b < d.n_batches; ++b) {
+        d.batch = b;
+        if ((rc = dense_sweep_batch(d, bv.d, ds, tr, st, s))) return rc;
+        ds.hub_slot = -1;  // the first batch folded the sequential pass into the totals
+    }
+    if (d.n_batches > 1) return dense_refresh_ends(d, bv.d, s);
+    return 0;
+}
+
+// ---------------------------------------------------------------- allocation-free sweep
+// Scratch of sbp_nodal_sweep_static, a file-scope device array: the decision
+// of every vertex (an int each, SBP_STATIC_MAX_VERTICES of them), the
+// evaluation's per-workgroup partials (STATIC_MAX_WGS + 1 slots) and one
+// statistics record for callers that pass none.  Every GPU the library runs
+// on holds its own copy until the process ends; calls on one GPU share it.
+// Nothing in it needs to start at zero: a sweep writes every decision and
+// partial it later reads.
+constexpr int STATIC_MAX_WGS = 4096;
+constexpr size_t STATIC_NB_BYTES = (size_t)SBP_STATIC_MAX_VERTICES * 4;
+constexpr size_t STATIC_PART_BYTES = (size_t)(STATIC_MAX_WGS + 1) * 4 * 8;
+constexpr size_t STATIC_SUM_BYTES = (size_t)(STATIC_MAX_WGS + 1) * 8;
+constexpr size_t STATIC_SCRATCH_BYTES = STATIC_NB_BYTES + STATIC_PART_BYTES + STATIC_SUM_BYTES + 256;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+struct StaticScratch {
+    int *nb;
+    long long *stats_part;
+    double *sum_part;
+    sbp_sweep_stats_dev *stats;
+};
+
+std::mutex g_static_mu;
+std::map<int, char *> g_static_ptr;  // device id -> address of that device's copy of scratch
+
+// The current device's copy of scratch, looked up once per device (the
+// array's name in host code is not a device address).
+int static_scratch(StaticScratch &sc) {
+    int dev = 0;
+    SBP_HIP_CHECK(hipGetDevice(&dev));
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        auto it = g_static_ptr.find(dev);
+        if (it == g_static_ptr.end()) {
+            void *ptr = nullptr;
+            SBP_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(SBP_E_HIP, "no device address for the static scratch array");
+            it = g_static_ptr.emplace(dev, (char *)ptr).first;
+        }
+        base = it->second;
+    }
+    sc.nb = (int *)base;
+    sc.stats_part = (long long *)(base + STATIC_NB_BYTES);
+    sc.sum_part = (double *)(base + STATIC_NB_BYTES + STATIC_PART_BYTES);
+    sc.stats = (sbp_sweep_stats_dev *)(base + STATIC_NB_BYTES + STATIC_PART_BYTES + STATIC_SUM_BYTES);
+    return 0;
+}
+
 int build_one(const GDev &d0, UnionLayout &u, BMView &bv, hipStream_t s) {
     std::vector<GDev> hG{d0};
     hG[0].action = ACT_NONE;
@@ -1019,11 +1118,7 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
                     const sbp_sweep_params *p, sbp_sweep_stats *stats, const sbp_sweep_trace *trace, void *ws,
                     size_t ws_bytes, void *stream) {
     int rc;
-    if ((rc = check_graph_args(g))) return rc;
-    if (!assign || !bm || !p || C < 1 || C > g->n || p->n_batches < 1 || p->eps < 0 || !(p->beta > 0))
-        return fail(SBP_E_ARG, "bad sweep arguments");
-    if (p->n_hubs < 0 || p->n_hubs > std::min(g->n, SBP_HUBS_MAX))
-        return fail(SBP_E_ARG, "n_hubs must lie in [0, min(n, 4096)]");
+    if ((rc = check_sweep_args(g, assign, C, bm, p))) return rc;
     BMView bv = bm_layout(bm, g->n, g->e, C);
     if (bm_bytes < bv.bytes) return fail(SBP_E_SPACE, "blockmodel storage too small");
     if (p->n_hubs > 0 && !bv.dense)
@@ -1036,24 +1131,10 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(1), 0, s, st);
         SBP_LAUNCH_CHECK();
     }
-    SweepTraceDev tr{};
-    if (trace) {
-        tr.prop = trace->prop;
-        tr.dS = trace->dS;
-        tr.lnH = trace->lnH;
-        tr.margin = trace->margin;
-        tr.accept = trace->accept;
-    }
-    GDev d = gdev_of(g, assign, C);
-    d.seed = p->seed;
-    d.sweep = p->sweep;
-    d.beta = p->beta;
-    d.eps = p->eps;
-    d.n_batches = std::min(p->n_batches, g->n);
-    d.action = ACT_SWEEP;
+    const SweepTraceDev tr = trace_of(trace);
+    GDev d = sweep_desc(g, assign, C, p);
     if (bv.dense) {
         DenseScratch ds{};
-        ds.delta = bv.delta;
         ds.nwg = dense_workgroups();
         ds.nb = w.nb_dense;
         ds.stats_part = w.stats_part;
@@ -1069,18 +1150,12 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         hs.codes = (int *)w.u.ws.v0;            // [2 cap >= 2e]
         hs.mpos = (int *)w.u.ws.v1;             // [2 cap >= 2e]
         hs.hubrank = w.hub;                     // [n]
-        if ((rc = dense_hub_pass(d, bv.d, ds, p->n_hubs, hs, tr, s))) return rc;
-        for (int b = 0; b < d.n_batches; ++b) {
-            d.batch = b;
-            if ((rc = dense_sweep_batch(d, bv.d, ds, tr, st, s))) return rc;
-            ds.hub_slot = -1;  // the first batch folded the sequential pass into the totals
-        }
-        if (d.n_batches > 1) return dense_refresh_ends(d, bv.d, s);
-        return 0;
+        return dense_sweep(d, bv, ds, p->n_hubs, hs, tr, st, s);
     }
+    SweepTraceDev trs = tr;
     // sparse tier: hub list, then per batch: evaluate + apply, rebuild
-    tr.status = w.status;
-    if (!tr.dS) tr.dS = w.dS;
+    trs.status = w.status;
+    if (!trs.dS) trs.dS = w.dS;
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.u.hub_count, 0);
     hipLaunchKernelGGL(k_hub_list, dim3(grid_for(g->n, BLK, 4096)), dim3(BLK), 0, s, g->out_ptr, g->in_ptr, g->n, w.hub,
                        w.u.hub_count);
@@ -1097,18 +1172,43 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         plan_step(hG, hm);
         if ((rc = upload_step(hG, hm, w.u, s))) return rc;
         SparseBM sbm = bv.sp;
-        if ((rc = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, tr, s))) return rc;
+        if ((rc = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, trs, s))) return rc;
         GDev d2 = d;
         d2.action = ACT_NONE;
         if ((rc = build_one(d2, w.u, bv, s))) return rc;
         const int nblk = std::max(1, std::min(dense_workgroups(), (int)((g->n / d.n_batches + 255) / 256)));
         hipLaunchKernelGGL(k_sweep_stats_part, dim3(nblk), dim3(256), 0, s, (const signed char *)w.status,
-                           (const double *)tr.dS, g->n, b, d.n_batches, w.stats_part, w.sum_part);
+                           (const double *)trs.dS, g->n, b, d.n_batches, w.stats_part, w.sum_part);
         hipLaunchKernelGGL(k_sweep_stats_final, dim3(1), dim3(64), 0, s, (const long long *)w.stats_part,
                            (const double *)w.sum_part, nblk, (const double *)bv.dl, st);
         SBP_LAUNCH_CHECK();
     }
     return 0;
+}
+
+int sbp_nodal_sweep_static(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, size_t bm_bytes,
+                           const sbp_sweep_params *p, sbp_sweep_stats *stats, const sbp_sweep_trace *trace,
+                           void *stream) {
+    int rc;
+    if ((rc = check_sweep_args(g, assign, C, bm, p))) return rc;
+    if (C > SBP_DENSE_MAX_C)
+        return fail(SBP_E_ARG, "the allocation-free sweep runs on the dense tier only (C <= 64)");
+    if (p->n_hubs != 0) return fail(SBP_E_ARG, "the allocation-free sweep has no hub pass (n_hubs must be 0)");
+    if (g->n > SBP_STATIC_MAX_VERTICES)
+        return fail(SBP_E_LIMIT, "the allocation-free sweep takes at most SBP_STATIC_MAX_VERTICES vertices");
+    BMView bv = bm_layout(bm, g->n, g->e, C);
+    if (bm_bytes < bv.bytes) return fail(SBP_E_SPACE, "blockmodel storage too small");
+    StaticScratch sc{};
+    if ((rc = static_scratch(sc))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    DenseScratch ds{};
+    ds.nwg = std::min(dense_workgroups(), STATIC_MAX_WGS);
+    ds.nb = sc.nb;
+    ds.stats_part = sc.stats_part;
+    ds.sum_part = sc.sum_part;
+    HubScratch hs{};
+    return dense_sweep(sweep_desc(g, assign, C, p), bv, ds, 0, hs, trace_of(trace),
+                       stats ? (sbp_sweep_stats_dev *)stats : sc.stats, s);
 }
 
 int sbp_merge_scores(const sbp_graph *g, const int32_t *assign, int32_t C, const void *bm, const sbp_merge_params *p,

@@ -80,6 +80,9 @@ _SIGS = {
     "sbp_nodal_sweep": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t,
                                    ct.POINTER(SweepParams), ct.c_void_p, ct.POINTER(SweepTrace), ct.c_void_p,
                                    ct.c_size_t, ct.c_void_p]),
+    "sbp_nodal_sweep_static": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t,
+                                          ct.POINTER(SweepParams), ct.c_void_p, ct.POINTER(SweepTrace),
+                                          ct.c_void_p]),
     "sbp_merge_scores": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(MergeParams),
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "sbp_merge_apply": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p,
@@ -241,10 +244,11 @@ def sbp_description_length(dg: DeviceGraph, C, bm):
 
 # ------------------------------------------------------------------ sweeps
 def sbp_nodal_sweep(dg: DeviceGraph, assign, C, bm, seed, sweep, beta=3.0, eps=1, n_batches=1, trace=True,
-                    stats=True, n_hubs=0):
+                    stats=True, n_hubs=0, static=False):
     """One sweep; assign and bm are updated in place.  Returns trace/stats dicts.
     n_hubs > 0: the hybrid sweep (the highest-degree vertices one at a time
-    first; dense tier only)."""
+    first; dense tier only).  static: the allocation-free entry point
+    (sbp_nodal_sweep_static; no workspace)."""
     p = SweepParams(seed, sweep, n_batches, beta, eps, n_hubs)
     tr = None
     out = {}
@@ -256,9 +260,14 @@ def sbp_nodal_sweep(dg: DeviceGraph, assign, C, bm, seed, sweep, beta=3.0, eps=1
         out["accept"] = torch.empty(dg.n, dtype=torch.int8, device=dg.device)
         tr = SweepTrace(*(out[k].data_ptr() for k in ("prop", "dS", "lnH", "margin", "accept")))
     st = torch.zeros(6, dtype=torch.float64, device=dg.device) if stats else None
-    ws = dg.workspace()
-    _check(lib().sbp_nodal_sweep(ct.byref(dg.struct), _ptr(assign), C, _ptr(bm), bm.numel(), ct.byref(p), _ptr(st),
-                                 ct.byref(tr) if tr is not None else None, _ptr(ws), ws.numel(), _stream()))
+    if static:
+        _check(lib().sbp_nodal_sweep_static(ct.byref(dg.struct), _ptr(assign), C, _ptr(bm), bm.numel(), ct.byref(p),
+                                            _ptr(st), ct.byref(tr) if tr is not None else None, _stream()))
+    else:
+        ws = dg.workspace()
+        _check(lib().sbp_nodal_sweep(ct.byref(dg.struct), _ptr(assign), C, _ptr(bm), bm.numel(), ct.byref(p),
+                                     _ptr(st), ct.byref(tr) if tr is not None else None, _ptr(ws), ws.numel(),
+                                     _stream()))
     res = {}
     if trace:
         res = {k: v.cpu().numpy() for k, v in out.items()}
