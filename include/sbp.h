@@ -235,6 +235,33 @@ int sbp_nodal_sweep_static(const sbp_graph *g /*[host]*/, int32_t *assign, int32
                            const sbp_sweep_params *p /*[host]*/, sbp_sweep_stats *stats,
                            const sbp_sweep_trace *trace /*[host]*/, void *stream);
 
+/* Replayable sweep (Alg. 2 batches captured once as a HIP graph).
+ * sbp_sweep_graph_create records one sweep of sbp_nodal_sweep with the
+ * given arguments (no trace) and instantiates it; nothing runs on the GPU.
+ * Each sbp_sweep_graph_launch then runs exactly that sweep on `stream`,
+ * except that the sweep index of the random stream is read from
+ * *sweep_index (one device uint32, set by the caller before the first
+ * launch) and the launch adds one to it when the sweep ends, so k launches
+ * equal k calls of sbp_nodal_sweep with sweep = s, s+1, ..., s+k-1 (same
+ * assign/bm/stats results, bit for bit).  `stats` (device) is required and
+ * rewritten by every launch.  The graph holds the addresses of g's arrays,
+ * assign, bm, sweep_index, stats and ws: they must stay allocated and
+ * unmoved, and the graph is used with the same C, until destroy.  Launches
+ * are ordered on their stream like kernels; launches of one graph on
+ * different streams, or of graphs sharing ws, race unless the caller orders
+ * them.  Limits: dense tier only (C <= SBP_DENSE_MAX_C, else SBP_E_ARG).
+ * The library allocates no device memory for the graph.  Errors: SBP_E_ARG,
+ * SBP_E_SPACE, SBP_E_HIP (capture or instantiation failed; *out = NULL). */
+typedef struct sbp_sweep_graph sbp_sweep_graph;
+int sbp_sweep_graph_create(const sbp_graph *g /*[host]*/, int32_t *assign, int32_t C, void *bm, size_t bm_bytes,
+                           const sbp_sweep_params *p /*[host]*/, uint32_t *sweep_index, sbp_sweep_stats *stats,
+                           void *ws, size_t ws_bytes, sbp_sweep_graph **out /*[host]*/);
+/* ASYNC on stream.  SBP_E_ARG for a NULL handle or a device other than the
+ * one current at creation. */
+int sbp_sweep_graph_launch(sbp_sweep_graph *graph, void *stream);
+/* Frees the graph (the caller orders this after its last launch ends). */
+int sbp_sweep_graph_destroy(sbp_sweep_graph *graph);
+
 /* ------------------------------------------------------------------ */
 /* Block merges (Alg. 1)                                               */
 /* ------------------------------------------------------------------ */

@@ -297,6 +297,7 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
             stats->sum_dS_accepted = (first ? 0.0 : stats->sum_dS_accepted) + sdt;
             stats->dl_after = dl;
         }
+        if (g.sweep_dev && g.action == ACT_SWEEP && g.batch == g.n_batches - 1) *g.sweep_dev += 1u;
     }
 }
 
@@ -335,6 +336,7 @@ struct EvalArgs {
     double beta;
     unsigned ftab_max, sweep;
     int n, C, batch, n_batches, eps, voff;
+    const unsigned *sweep_dev;  // nullable: the sweep index in device memory
 };
 
 // Static LDS of the evaluation kernel for up to CM blocks: every array sits at
@@ -415,6 +417,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
     }
     long long n_prop = 0, n_self = 0, n_acc = 0;
     double s_dS = 0.0;
+    const unsigned sweep = a.sweep_dev ? *a.sweep_dev : a.sweep;
     const int nbc = (a.n - a.batch + a.n_batches - 1) / a.n_batches;
     const int nchunks = (nbc + CH - 1) / CH;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -437,8 +440,8 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
                 L.kin[tid] = ki;
                 k = ko + ki;
                 uint32_t wa[4], wb[4];
-                philox_block((uint32_t)v, a.sweep, 0u, 0u, k0, k1, wa);
-                philox_block((uint32_t)v, a.sweep, 1u, 0u, k0, k1, wb);
+                philox_block((uint32_t)v, sweep, 0u, 0u, k0, k1, wa);
+                philox_block((uint32_t)v, sweep, 1u, 0u, k0, k1, wb);
                 const uint64_t W0 = (uint64_t)wa[0] | ((uint64_t)wa[1] << 32);
                 L.W[0][tid] = (uint64_t)wa[2] | ((uint64_t)wa[3] << 32);
                 L.W[1][tid] = (uint64_t)wb[0] | ((uint64_t)wb[1] << 32);
@@ -1190,7 +1193,7 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
     const bool mirrored = bm.flags[0] == 1;
     // wave 1 draws hub i's words while wave 0 scores hub i - 1
     auto draw_hub = [&](int vv, int kvv, int slot_) {
-        const Words4 W = draw_words(g.seed, (uint32_t)vv, g.sweep, 0u, 0u);
+        const Words4 W = draw_words(g.seed, (uint32_t)vv, sweep_of(g), 0u, 0u);
         const int kk_ = (kvv & 0xffff) + (kvv >> 16);
         if (lane == 0) {
             s_W[slot_][0] = W.w[1];
@@ -1643,6 +1646,7 @@ int run_eval(const GDev &g, const DenseBM &bm, DenseScratch &ws, const SweepTrac
     a.beta = g.beta;
     a.ftab_max = bm.ftab_max;
     a.sweep = g.sweep;
+    a.sweep_dev = g.sweep_dev;
     a.n = g.n;
     a.C = g.C;
     a.batch = g.batch;

@@ -159,7 +159,11 @@ struct GDev {
     unsigned sweep, phase;
     double beta;
     int eps, n_batches, batch, proposals;
+    // nullable: the sweep index is read from here instead of `sweep` (a
+    // replayed graph), and the last batch's final step adds one to it
+    unsigned *sweep_dev;
 };
+__device__ __forceinline__ unsigned sweep_of(const GDev &g) { return g.sweep_dev ? *g.sweep_dev : g.sweep; }
 
 // Per-step flat work lists: starts[g] is graph g's first item (graphs with
 // no items in a list get an empty range at the right place).

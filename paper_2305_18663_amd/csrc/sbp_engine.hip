@@ -47,6 +47,8 @@ static std::map<std::string, ProfRec> g_prof;
 ProfileScope::ProfileScope(const char *name, hipStream_t stream, bool attach) : s(stream), attach_(attach) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (g_prof_stride <= 0) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;  // no timing events inside a captured graph
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (g_prof[name].calls++ % g_prof_stride != 0) return;  // not a sampled launch
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return;
@@ -546,6 +548,24 @@ int dense_sweep(GDev d, BMView &bv, DenseScratch &ds, int n_hubs, const HubScrat
     return 0;
 }
 
+// The dense tier's scratch inside a single-graph workspace.
+void dense_scratch_of(const SingleWS &w, DenseScratch &ds, HubScratch &hs) {
+    ds.nwg = dense_workgroups();
+    ds.nb = w.nb_dense;
+    ds.stats_part = w.stats_part;
+    ds.sum_part = w.sum_part;
+    // hybrid schedule: the hubs one at a time, then the batches without them
+    hs.k0 = w.u.ws.k0;
+    hs.k1 = w.u.ws.k1;
+    hs.temp = w.u.ws.temp;
+    hs.order = w.u.ws.i0;        // [cap >= n]
+    hs.kk = w.u.ws.i1;           // [cap >= n]
+    hs.hoff = (int *)w.u.ws.s0;  // [2 (cap + 1) >= n + 1]
+    hs.codes = (int *)w.u.ws.v0; // [2 cap >= 2e]
+    hs.mpos = (int *)w.u.ws.v1;  // [2 cap >= 2e]
+    hs.hubrank = w.hub;          // [n]
+}
+
 // ---------------------------------------------------------------- allocation-free sweep
 // Scratch of sbp_nodal_sweep_static, a file-scope device array: the decision
 // of every vertex (an int each, SBP_STATIC_MAX_VERTICES of them), the
@@ -661,6 +681,11 @@ struct sbp_engine_impl {
 }  // namespace sbp
 
 struct sbp_engine : public sbp::sbp_engine_impl {};
+struct sbp_sweep_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int dev;
+};
 
 namespace sbp {
 namespace {
@@ -1135,21 +1160,8 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     GDev d = sweep_desc(g, assign, C, p);
     if (bv.dense) {
         DenseScratch ds{};
-        ds.nwg = dense_workgroups();
-        ds.nb = w.nb_dense;
-        ds.stats_part = w.stats_part;
-        ds.sum_part = w.sum_part;
-        // hybrid schedule: the hubs one at a time, then the batches without them
         HubScratch hs{};
-        hs.k0 = w.u.ws.k0;
-        hs.k1 = w.u.ws.k1;
-        hs.temp = w.u.ws.temp;
-        hs.order = w.u.ws.i0;                   // [cap >= n]
-        hs.kk = w.u.ws.i1;                      // [cap >= n]
-        hs.hoff = (int *)w.u.ws.s0;             // [2 (cap + 1) >= n + 1]
-        hs.codes = (int *)w.u.ws.v0;            // [2 cap >= 2e]
-        hs.mpos = (int *)w.u.ws.v1;             // [2 cap >= 2e]
-        hs.hubrank = w.hub;                     // [n]
+        dense_scratch_of(w, ds, hs);
         return dense_sweep(d, bv, ds, p->n_hubs, hs, tr, st, s);
     }
     SweepTraceDev trs = tr;
@@ -1209,6 +1221,69 @@ int sbp_nodal_sweep_static(const sbp_graph *g, int32_t *assign, int32_t C, void 
     HubScratch hs{};
     return dense_sweep(sweep_desc(g, assign, C, p), bv, ds, 0, hs, trace_of(trace),
                        stats ? (sbp_sweep_stats_dev *)stats : sc.stats, s);
+}
+
+int sbp_sweep_graph_create(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, size_t bm_bytes,
+                           const sbp_sweep_params *p, uint32_t *sweep_index, sbp_sweep_stats *stats, void *ws,
+                           size_t ws_bytes, sbp_sweep_graph **out) {
+    int rc;
+    if (!out) return fail(SBP_E_ARG, "null output handle");
+    *out = nullptr;
+    if ((rc = check_sweep_args(g, assign, C, bm, p))) return rc;
+    if (!sweep_index || !stats) return fail(SBP_E_ARG, "the sweep index and the statistics record are required");
+    if (C > SBP_DENSE_MAX_C) return fail(SBP_E_ARG, "a captured sweep runs on the dense tier only (C <= 64)");
+    BMView bv = bm_layout(bm, g->n, g->e, C);
+    if (bm_bytes < bv.bytes) return fail(SBP_E_SPACE, "blockmodel storage too small");
+    SingleWS w = single_layout(ws, ws_bytes, g->n, g->e);
+    if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
+    DenseScratch ds{};
+    HubScratch hs{};
+    dense_scratch_of(w, ds, hs);
+    GDev d = sweep_desc(g, assign, C, p);
+    d.sweep_dev = sweep_index;
+    // capture on a private stream of the default priority, so that the
+    // caller's stream (possibly the legacy null stream) is never in capture
+    hipStream_t cs = nullptr;
+    SBP_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = dense_sweep(d, bv, ds, p->n_hubs, hs, trace_of(nullptr), (sbp_sweep_stats_dev *)stats, cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (!rc && e2 != hipSuccess) rc = fail(SBP_E_HIP, std::string("stream capture: ") + hipGetErrorString(e2));
+        if (!rc && (e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+            rc = fail(SBP_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    } else {
+        rc = fail(SBP_E_HIP, std::string("stream capture: ") + hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    *out = new sbp_sweep_graph{graph, exec, dev};
+    return 0;
+}
+
+int sbp_sweep_graph_launch(sbp_sweep_graph *h, void *stream) {
+    if (!h) return fail(SBP_E_ARG, "null graph handle");
+    int dev = 0;
+    SBP_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != h->dev) return fail(SBP_E_ARG, "the graph was captured on another device");
+    SBP_HIP_CHECK(hipGraphLaunch(h->exec, (hipStream_t)stream));
+    return 0;
+}
+
+int sbp_sweep_graph_destroy(sbp_sweep_graph *h) {
+    if (!h) return 0;
+    const hipError_t a = hipGraphExecDestroy(h->exec), b = hipGraphDestroy(h->graph);
+    delete h;
+    if (a != hipSuccess || b != hipSuccess) return fail(SBP_E_HIP, "graph destruction failed");
+    return 0;
 }
 
 int sbp_merge_scores(const sbp_graph *g, const int32_t *assign, int32_t C, const void *bm, const sbp_merge_params *p,

@@ -83,6 +83,11 @@ _SIGS = {
     "sbp_nodal_sweep_static": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t,
                                           ct.POINTER(SweepParams), ct.c_void_p, ct.POINTER(SweepTrace),
                                           ct.c_void_p]),
+    "sbp_sweep_graph_create": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_size_t,
+                                          ct.POINTER(SweepParams), ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                          ct.c_size_t, ct.POINTER(ct.c_void_p)]),
+    "sbp_sweep_graph_launch": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "sbp_sweep_graph_destroy": (ct.c_int, [ct.c_void_p]),
     "sbp_merge_scores": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(MergeParams),
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "sbp_merge_apply": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p,
@@ -273,11 +278,55 @@ def sbp_nodal_sweep(dg: DeviceGraph, assign, C, bm, seed, sweep, beta=3.0, eps=1
         res = {k: v.cpu().numpy() for k, v in out.items()}
         res["accept"] = res["accept"].astype(bool)
     if stats:
-        raw = st.cpu().numpy()
-        ints = raw[:4].view(np.int64)
-        res.update(proposals=int(ints[0]), self_proposals=int(ints[1]), accepted=int(ints[2]),
-                   sum_dS=float(raw[4]), dl_after=float(raw[5]))
+        res.update(_stats_dict(st))
     return res
+
+
+def _stats_dict(st):
+    raw = st.cpu().numpy()
+    ints = raw[:4].view(np.int64)
+    return dict(proposals=int(ints[0]), self_proposals=int(ints[1]), accepted=int(ints[2]),
+                sum_dS=float(raw[4]), dl_after=float(raw[5]))
+
+
+class SweepGraph:
+    """One sweep captured as a HIP graph (sbp_sweep_graph_create); every
+    launch() runs the next sweep: it reads the sweep index from device
+    memory and advances it.  assign, bm and the graph must stay alive and
+    unmoved while this object lives (it keeps references to them)."""
+
+    def __init__(self, dg: DeviceGraph, assign, C, bm, seed, sweep, beta=3.0, eps=1, n_batches=1, n_hubs=0):
+        self.dg, self.assign, self.bm = dg, assign, bm
+        self.ws = _buffer(lib().sbp_workspace_bytes(0, dg.n, dg.e, 1), dg.device)
+        self.index = torch.full((1,), int(sweep), dtype=torch.int32, device=dg.device)
+        self.st = torch.zeros(6, dtype=torch.float64, device=dg.device)
+        p = SweepParams(seed, sweep, n_batches, beta, eps, n_hubs)
+        h = ct.c_void_p()
+        _check(lib().sbp_sweep_graph_create(ct.byref(dg.struct), _ptr(assign), C, _ptr(bm), bm.numel(), ct.byref(p),
+                                            _ptr(self.index), _ptr(self.st), _ptr(self.ws), self.ws.numel(),
+                                            ct.byref(h)))
+        self.h = h
+
+    def launch(self):
+        _check(lib().sbp_sweep_graph_launch(self.h, _stream()))
+
+    def sweep_index(self):
+        return int(self.index.cpu()[0])
+
+    def stats(self):
+        return _stats_dict(self.st)
+
+    def close(self):
+        if self.h:
+            torch.cuda.current_stream().synchronize()
+            _check(lib().sbp_sweep_graph_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ merges

@@ -87,3 +87,12 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(sbp, "LIB_PATH", "/nonexistent/libsbp.so")
     with pytest.raises(RuntimeError, match="missing"):
         sbp.lib()
+
+
+def test_autotune_bins_and_missing_cache(tmp_path):
+    from paper_2305_18663_amd import autotune
+    assert autotune.size_bin(200_000, 4_000_000, 45) == "n17_k22_c2_b1"
+    assert autotune.size_bin(1000, 8000, 10, 3) == "n9_k13_c1_b3"
+    assert autotune.size_bin(1, 0, 1) == "n0_k0_c0_b1"
+    # no cache: the defaults are set and returned
+    assert autotune.apply(str(tmp_path / "none.json"), 1000, 8000, 10) == autotune.DEFAULTS
