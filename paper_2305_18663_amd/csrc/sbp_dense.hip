@@ -385,15 +385,52 @@ constexpr int eval_wgs_per_cu() {
 //      the three logs of the wave's eight vertices in one evaluation.
 // The decision goes to nb: with ENDS one byte per vertex (0xff = stays),
 // otherwise an int (-1 = stays).  TRACE adds the per-vertex record.
-template <bool ENDS, bool TRACE, int CM>
-__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTraceDev tr) {
+//
+// The chunks a workgroup takes come from a chunk source: the strided split of
+// one graph's chunks over the grid (StridedChunks), or runs of consecutive
+// chunks pulled from a graph's work queue (QueueChunks).
+struct StridedChunks {
+    int cur, stride, n;
+    __device__ __forceinline__ int first(int nchunks) {
+        n = nchunks;
+        return cur < n ? cur : -1;
+    }
+    __device__ __forceinline__ int next() {
+        cur += stride;
+        return cur < n ? cur : -1;
+    }
+};
+// Runs of `run_len` consecutive chunks; `cur` starts as the first chunk of a
+// run already taken.  A new run is pulled with one atomic by thread 0 and one
+// barrier; the pulled index is read before the next barrier of the chunk loop,
+// so the next pull cannot overwrite it early.
+struct QueueChunks {
+    int *ctr;      // the graph's queue: next run index
+    int *pull;     // LDS word for the pulled index
+    int run_len, cur, end, n;
+    __device__ __forceinline__ int first(int nchunks) {
+        n = nchunks;
+        end = min(cur + run_len, n);
+        return cur < n ? cur : -1;
+    }
+    __device__ __forceinline__ int next() {
+        if (++cur < end) return cur;
+        if (threadIdx.x == 0) *pull = atomicAdd(ctr, 1);
+        __syncthreads();
+        cur = __builtin_amdgcn_readfirstlane(*pull) * run_len;
+        end = min(cur + run_len, n);
+        return cur < n ? cur : -1;
+    }
+};
+
+template <bool ENDS, bool TRACE, int CM, class Chunks>
+__device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, const SweepTraceDev &tr, Chunks src) {
     using Lds = EvalLds<CM>;
     constexpr int CH = Lds::CH;
     constexpr int RS = Lds::RS;
     constexpr int NQ = CM / GS;  // blocks per lane in the scoring phase
     constexpr int BQ = NQ < 2 ? NQ : 2;  // slots per batch of table gathers
     static_assert(CH % NG == 0, "every group scores the same number of vertices per chunk");
-    __shared__ Lds L;
     const double *__restrict__ tab = a.ftab;
     const unsigned fmax = a.ftab_max;
     const int C = a.C;
@@ -421,7 +458,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
     const int nbc = (a.n - a.batch + a.n_batches - 1) / a.n_batches;
     const int nchunks = (nbc + CH - 1) / CH;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    for (int chunk = src.first(nchunks); chunk >= 0; chunk = src.next()) {
         const int base = chunk * CH;
         const int nv = min(CH, nbc - base);
         __syncthreads();  // previous chunk done with the LDS
@@ -758,6 +795,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
             }
         }
     }
+    if (!a.stats_part) return;  // uniform: the multi-graph pass keeps no statistics
     n_prop = wave_sum_i64(n_prop);
     n_self = wave_sum_i64(n_self);
     n_acc = wave_sum_i64(n_acc);
@@ -785,6 +823,84 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
         a.stats_part[4 * blockIdx.x + 3] = 0;
         a.sum_part[blockIdx.x] = sd;
     }
+}
+
+template <bool ENDS, bool TRACE, int CM>
+__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTraceDev tr) {
+    __shared__ EvalLds<CM> L;
+    eval_body<ENDS, TRACE, CM>(L, a, tr, StridedChunks{(int)blockIdx.x, (int)gridDim.x, 0});
+}
+
+// Many graphs in one persistent launch, each with its own work queue of chunk
+// runs (ctr[g] counts the runs taken, nruns[g] of them exist).  A workgroup
+// starts at the graph its index falls in (spread by work), drains that
+// graph's queue, then moves on to the next graph with work left; it ends after
+// finding every queue empty once in a row, so every workgroup exits.  The
+// graph's blockmodel is staged in LDS each time a workgroup starts on a
+// graph.  Decisions are ints (the labels are gathered, no end bytes), no
+// statistics and no trace.
+template <int CM>
+__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval_multi(const EvalArgs *__restrict__ A,
+                                                               const int *__restrict__ nruns,
+                                                               const int *__restrict__ gstart, int *__restrict__ ctr,
+                                                               int D, int run_len) {
+    __shared__ EvalLds<CM> L;
+    __shared__ int pull;
+    // first graph: the one whose share of the grid holds this workgroup
+    int g = 0;
+    {
+        int lo = 0, hi = D - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (gstart[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        g = lo;
+    }
+    int misses = 0;
+    while (misses < D) {
+        if (threadIdx.x == 0) pull = atomicAdd(&ctr[g], 1);
+        __syncthreads();
+        const int run = __builtin_amdgcn_readfirstlane(pull);
+        if (run < nruns[g]) {
+            misses = 0;
+            const EvalArgs a = A[g];
+            eval_body<false, false, CM>(L, a, SweepTraceDev{},
+                                        QueueChunks{&ctr[g], &pull, run_len, run * run_len, 0, 0});
+        } else {
+            ++misses;
+        }
+        __syncthreads();  // the LDS and the pulled index are free again
+        g = g + 1 == D ? 0 : g + 1;
+    }
+}
+
+// Dense copy of one graph's part of the union sparse blockmodel (one
+// workgroup per graph): M from its C rows, f(M), block degrees; also empties
+// the graph's work queue for the evaluation that follows.
+struct ToDense {
+    int boff, C;
+    int *M;
+    double *fM;
+    int *dout, *din;
+};
+__global__ void __launch_bounds__(256) k_to_dense(const ToDense *__restrict__ J, SparseBM bm,
+                                                  const double *__restrict__ tab, unsigned fmax,
+                                                  int *__restrict__ ctr) {
+    const ToDense j = J[blockIdx.x];
+    const int C = j.C, CC = C * C, tid = threadIdx.x;
+    for (int i = tid; i < CC; i += 256) j.M[i] = 0;
+    __syncthreads();
+    for (int a = 0; a < C; ++a) {
+        const int p0 = bm.rptr[j.boff + a], p1 = bm.rptr[j.boff + a + 1];
+        for (int q = p0 + tid; q < p1; q += 256) j.M[a * C + (bm.rcol[q] - j.boff)] = bm.rval[q];
+    }
+    __syncthreads();
+    for (int i = tid; i < CC; i += 256) j.fM[i] = fx(tab, fmax, j.M[i]);
+    if (tid < C) {
+        j.dout[tid] = bm.dout[j.boff + tid];
+        j.din[tid] = bm.din[j.boff + tid];
+    }
+    if (tid == 0) ctr[blockIdx.x] = 0;
 }
 
 // After the decisions of a single-batch sweep: every edge end once, chunks of
@@ -1706,6 +1822,131 @@ int dense_sweep_batch(const GDev &g, DenseBM &bm, DenseScratch &ws, const SweepT
                        ws.stats_part, ws.sum_part, grid, stats, one ? (const unsigned char *)ws.nb : nullptr,
                        g.batch == 0 ? ws.hub_slot : -1);
     SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+// Engine path: one sweep batch of every listed graph on the dense kernels,
+// against the union sparse blockmodel built for this step.  Per graph: a dense
+// copy of its blockmodel in its slot, then one persistent evaluation launch
+// per block-capacity class with a work queue per graph.  Decisions go to each
+// job's nb as ints (-1 = stays); the caller applies them.
+size_t dense_multi_scratch_bytes(int max_graphs) {
+    const size_t G = (size_t)(max_graphs > 0 ? max_graphs : 1);
+    return ((G * sizeof(EvalArgs) + 255) & ~(size_t)255) + ((G * sizeof(ToDense) + 255) & ~(size_t)255) +
+           3 * ((G * sizeof(int) + 255) & ~(size_t)255) + 256;
+}
+
+void fill_ftab(double *tab, unsigned n_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_ftab, dim3(grid_for((long long)n_max + 1, 256, 8192)), dim3(256), 0, s, tab, n_max);
+}
+
+int dense_multi_sweep(const std::vector<DenseSweepJob> &jobs, const SparseBM &bm, const double *ftab,
+                      unsigned ftab_max, void *scratch, int max_graphs, hipStream_t s) {
+    const int D = (int)jobs.size();
+    if (D == 0) return 0;
+    if (D > max_graphs) return fail(-1, "more dense sweeps than the engine's graphs");
+    char *b = (char *)scratch;
+    const size_t G = (size_t)max_graphs;
+    EvalArgs *dA = (EvalArgs *)b;
+    b += (G * sizeof(EvalArgs) + 255) & ~(size_t)255;
+    ToDense *dJ = (ToDense *)b;
+    b += (G * sizeof(ToDense) + 255) & ~(size_t)255;
+    int *d_nruns = (int *)b;
+    b += (G * sizeof(int) + 255) & ~(size_t)255;
+    int *d_gstart = (int *)b;
+    b += (G * sizeof(int) + 255) & ~(size_t)255;
+    int *d_ctr = (int *)b;
+    // jobs ordered by block-capacity class
+    std::vector<int> order(D);
+    auto cls = [&](int C) { return C <= 16 ? 0 : C <= 32 ? 1 : C <= 48 ? 2 : 3; };
+    int pos = 0;
+    int cstart[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) {
+        cstart[c] = pos;
+        for (int i = 0; i < D; ++i)
+            if (cls(jobs[i].g.C) == c) order[pos++] = i;
+    }
+    cstart[4] = pos;
+    const int chunk_of[4] = {eval_chunk<16>(), eval_chunk<32>(), eval_chunk<48>(), eval_chunk<64>()};
+    const int per_cu[4] = {eval_wgs_per_cu<16>(), eval_wgs_per_cu<32>(), eval_wgs_per_cu<48>(), eval_wgs_per_cu<64>()};
+    const int cus = dense_workgroups() / 4;
+    std::vector<EvalArgs> hA(D);
+    std::vector<ToDense> hJ(D);
+    std::vector<int> nruns(D), gstart(D);
+    int grid[4] = {0, 0, 0, 0}, run_len[4] = {1, 1, 1, 1};
+    for (int c = 0; c < 4; ++c) {
+        long long total = 0;
+        for (int k = cstart[c]; k < cstart[c + 1]; ++k) {
+            const GDev &g = jobs[order[k]].g;
+            const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
+            total += (nbc + chunk_of[c] - 1) / chunk_of[c];
+        }
+        if (total == 0) continue;
+        grid[c] = (int)std::min<long long>(total, (long long)cus * per_cu[c]);
+        // about four runs per workgroup, so that late workgroups can balance
+        run_len[c] = (int)std::max<long long>(1, std::min<long long>(64, total / (4LL * grid[c])));
+        long long acc = 0;
+        for (int k = cstart[c]; k < cstart[c + 1]; ++k) {
+            const GDev &g = jobs[order[k]].g;
+            const int nbc = (g.n - g.batch + g.n_batches - 1) / g.n_batches;
+            const int nch = (nbc + chunk_of[c] - 1) / chunk_of[c];
+            nruns[k] = (nch + run_len[c] - 1) / run_len[c];
+            gstart[k] = (int)(acc * grid[c] / total);  // first workgroup of the graph's share
+            acc += nch;
+        }
+    }
+    for (int k = 0; k < D; ++k) {
+        const DenseSweepJob &j = jobs[order[k]];
+        const GDev &g = j.g;
+        EvalArgs a{};
+        a.out_ptr = g.out_ptr;
+        a.in_ptr = g.in_ptr;
+        a.out_idx = g.out_idx;
+        a.in_idx = g.in_idx;
+        a.lab = g.lab;
+        a.M = j.M;
+        a.dout = j.dout;
+        a.din = j.din;
+        a.fM = j.fM;
+        a.ftab = ftab;
+        a.ftab_max = ftab_max;
+        a.nb = j.nb;
+        a.seed = g.seed;
+        a.beta = g.beta;
+        a.sweep = g.sweep;
+        a.n = g.n;
+        a.C = g.C;
+        a.batch = g.batch;
+        a.n_batches = g.n_batches;
+        a.eps = g.eps;
+        hA[k] = a;
+        hJ[k] = ToDense{g.boff, g.C, j.M, j.fM, j.dout, j.din};
+    }
+    SBP_HIP_CHECK(hipMemcpyAsync(dA, hA.data(), D * sizeof(EvalArgs), hipMemcpyHostToDevice, s));
+    SBP_HIP_CHECK(hipMemcpyAsync(dJ, hJ.data(), D * sizeof(ToDense), hipMemcpyHostToDevice, s));
+    SBP_HIP_CHECK(hipMemcpyAsync(d_nruns, nruns.data(), D * sizeof(int), hipMemcpyHostToDevice, s));
+    SBP_HIP_CHECK(hipMemcpyAsync(d_gstart, gstart.data(), D * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_to_dense, dim3(D), dim3(256), 0, s, (const ToDense *)dJ, bm, ftab, ftab_max, d_ctr);
+    SBP_LAUNCH_CHECK();
+    for (int c = 0; c < 4; ++c) {
+        const int n = cstart[c + 1] - cstart[c];
+        if (n == 0 || grid[c] == 0) continue;
+        const int o = cstart[c];
+        ProfileScope prof("sweep_eval_multi", s);
+        if (c == 0)
+            hipLaunchKernelGGL(k_dense_eval_multi<16>, dim3(grid[c]), dim3(EVAL_T), 0, s, (const EvalArgs *)dA + o,
+                               (const int *)d_nruns + o, (const int *)d_gstart + o, d_ctr + o, n, run_len[c]);
+        else if (c == 1)
+            hipLaunchKernelGGL(k_dense_eval_multi<32>, dim3(grid[c]), dim3(EVAL_T), 0, s, (const EvalArgs *)dA + o,
+                               (const int *)d_nruns + o, (const int *)d_gstart + o, d_ctr + o, n, run_len[c]);
+        else if (c == 2)
+            hipLaunchKernelGGL(k_dense_eval_multi<48>, dim3(grid[c]), dim3(EVAL_T), 0, s, (const EvalArgs *)dA + o,
+                               (const int *)d_nruns + o, (const int *)d_gstart + o, d_ctr + o, n, run_len[c]);
+        else
+            hipLaunchKernelGGL(k_dense_eval_multi<64>, dim3(grid[c]), dim3(EVAL_T), 0, s, (const EvalArgs *)dA + o,
+                               (const int *)d_nruns + o, (const int *)d_gstart + o, d_ctr + o, n, run_len[c]);
+        SBP_LAUNCH_CHECK();
+    }
     return 0;
 }
 

@@ -181,7 +181,9 @@ struct StepMeta {
     long long Ntot, Etot;
 };
 
-enum { ACT_NONE = 0, ACT_SWEEP = 1, ACT_MERGE = 2, ACT_COMPACT = 3 };
+// ACT_DSWEEP: a sweep batch evaluated by the dense kernels (engine, C <= 64);
+// the union kernels only apply its decisions.
+enum { ACT_NONE = 0, ACT_SWEEP = 1, ACT_MERGE = 2, ACT_COMPACT = 3, ACT_DSWEEP = 4 };
 
 #define SBP_LEAF_MAX 256
 #define SBP_DENSE_MAX_C_DEV 64

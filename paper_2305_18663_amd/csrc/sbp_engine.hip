@@ -310,8 +310,17 @@ struct UnionLayout {
     double *dS, *dSl; // [N]
     int *hub_count;   // device counter for on-the-fly hub lists
     int *flags;       // validation flags
+    double *ftab;     // f(x) = x ln x for 0 <= x <= max(E, 1): no count of any graph exceeds it
+    unsigned ftab_max;
+    char *dslots;     // per engine slot: dense M, f(M) and degrees for C <= 64
+    void *dmulti;     // launch tables of the multi-graph dense sweep
     size_t bytes;
 };
+
+// One engine slot's dense blockmodel: M [64*64] ints, f(M) [64*64] doubles,
+// degrees [64] + [64] ints (rows packed at the graph's own C).
+constexpr size_t DSLOT_BYTES = 64 * 64 * 4 + 64 * 64 * 8 + 2 * 64 * 4;
+int g_engine_dense_max_c = SBP_DENSE_MAX_C;  // engine sweeps at C <= this use the dense kernels (0: never)
 
 UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     UnionLayout u{};
@@ -361,6 +370,10 @@ UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     u.dSl = a.take<double>(N);
     u.hub_count = a.take<int>(1);
     u.flags = a.take<int>(4);
+    u.ftab_max = (unsigned)std::max<long long>(E, 1);
+    u.ftab = a.take<double>((size_t)u.ftab_max + 1);
+    u.dslots = a.take<char>(DSLOT_BYTES * (size_t)G);
+    u.dmulti = a.take<char>(dense_multi_scratch_bytes(G));
     u.bytes = a.used;
     return u;
 }
@@ -922,6 +935,7 @@ int engine_step(sbp_engine *eng, int *active_out) {
     }
     // 6: actions against the blockmodel built above (same layout)
     bool any_act = false;
+    std::vector<DenseSweepJob> djobs;
     for (int g = 0; g < G; ++g) {
         GraphRun &r = *eng->active[g];
         GDev d = desc_of(r);
@@ -930,6 +944,19 @@ int engine_step(sbp_engine *eng, int *active_out) {
         d.eoff = hG[g].eoff;
         d.C = r.C;
         if (r.action == ACT_MERGE) d.C = r.C0;
+        if (r.action == ACT_SWEEP && d.C <= g_engine_dense_max_c) {
+            // the dense kernels evaluate it; the union kernels apply it
+            d.action = ACT_DSWEEP;
+            char *slot = u.dslots + DSLOT_BYTES * (size_t)r.eslot;
+            DenseSweepJob j;
+            j.g = d;
+            j.M = (int *)slot;
+            j.fM = (double *)(slot + 64 * 64 * 4);
+            j.dout = (int *)(slot + 64 * 64 * 12);
+            j.din = j.dout + 64;
+            j.nb = u.ws.nb + d.voff;
+            djobs.push_back(j);
+        }
         hG[g] = d;
         any_act |= r.action != ACT_NONE;
     }
@@ -943,7 +970,10 @@ int engine_step(sbp_engine *eng, int *active_out) {
         am.m.n_chunks = hm.m.n_chunks;
         if ((rc = upload_step(hG, am, u, s))) return rc;
         SweepTraceDev tr{};
-        if (am.m.n_leaf + am.m.n_hub > 0) {
+        if (!djobs.empty() &&
+            (rc = dense_multi_sweep(djobs, bm, u.ftab, u.ftab_max, u.dmulti, eng->maxG, s)))
+            return rc;
+        if (am.m.n_leaf + am.m.n_hub > 0 || !djobs.empty()) {
             StepMeta sm = am.m;
             sm.leaf = am.m.leaf;
             if ((rc = union_sweep(u.dG, sm, bm, u.ws, tr, s))) return rc;
@@ -1391,6 +1421,8 @@ int sbp_engine_create(void *ws, size_t ws_bytes, int64_t max_vertices, int64_t m
     eng->maxG = max_graphs;
     Arena a(ws, ws_bytes);
     eng->u = union_layout(a, max_vertices, max_edges, max_graphs);
+    fill_ftab(eng->u.ftab, eng->u.ftab_max, eng->s);
+    SBP_LAUNCH_CHECK();
     const size_t pool_off = a.used;
     eng->pool_bytes = ws_bytes - pool_off;
     eng->free_list.push_back({pool_off, eng->pool_bytes});
@@ -1556,6 +1588,10 @@ int sbp_partition(const sbp_graph *g, const int32_t *assign_in, int32_t C_in, co
 
 int sbp_tune(const char *key, int64_t value) {
     if (!key) return fail(SBP_E_ARG, "null key");
+    if (!strcmp(key, "engine_dense_max_c") && value >= 0 && value <= SBP_DENSE_MAX_C) {
+        g_engine_dense_max_c = (int)value;
+        return 0;
+    }
     if (dense_tune(key, (long long)value) == 0) return 0;
     return fail(SBP_E_ARG, std::string("unknown tuning key or value: ") + key);
 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "sbp_device.h"
 
@@ -211,5 +212,20 @@ int dense_merge_scores(const GDev &g, const DenseBM &bm, int *partner, double *d
 int dense_refresh_ends(const GDev &g, DenseBM &bm, hipStream_t s);
 int dense_workgroups();
 int dense_tune(const char *key, long long value);
+// One graph's sweep batch on the engine's dense path: the graph (labels, CSR,
+// C, seed, sweep index, batch, eps, beta; boff = its first union block), its
+// dense slot (M and f(M) [C*C], degrees [C]) and its decisions [n] (ints,
+// -1 = stays).
+struct DenseSweepJob {
+    GDev g;
+    int *M;
+    double *fM;
+    int *dout, *din;
+    int *nb;
+};
+size_t dense_multi_scratch_bytes(int max_graphs);
+void fill_ftab(double *tab, unsigned n_max, hipStream_t s);
+int dense_multi_sweep(const std::vector<DenseSweepJob> &jobs, const SparseBM &bm, const double *ftab,
+                      unsigned ftab_max, void *scratch, int max_graphs, hipStream_t s);
 
 }  // namespace sbp

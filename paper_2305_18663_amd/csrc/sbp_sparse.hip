@@ -1210,7 +1210,7 @@ __global__ void k_sweep_apply(const GDev *__restrict__ G, const int *__restrict_
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Ntot; i += gridDim.x * blockDim.x) {
         const int g = find_graph(vstart, nG, i);
         const GDev &d = G[g];
-        if (d.action != ACT_SWEEP) continue;
+        if (d.action != ACT_SWEEP && d.action != ACT_DSWEEP) continue;
         const int v = i - d.voff;
         if ((v % d.n_batches) != d.batch) continue;
         const int x = nb[i];

@@ -583,6 +583,26 @@ def test_batch_equals_alone():
         assert np.array_equal(batch[i]["trace"], alone["trace"])
 
 
+@pytest.mark.parametrize("n_batches", [1, 3])
+def test_engine_dense_sweeps_equal_sparse_sweeps(n_batches):
+    # sweeps at C <= 64 run on the multi-graph dense kernels inside the engine;
+    # switching them off (every sweep on the sparse kernels) changes nothing
+    sizes = [500, 3000, 900, 12000, 1500, 700]
+    graphs = [gen.batch_graph(n, seed=3300 + i) for i, n in enumerate(sizes)]
+    dgs = [sbp.DeviceGraph(g) for g in graphs]
+    kw = [dict(seed=600 + i, n_batches=n_batches) for i in range(len(graphs))]
+    try:
+        dense = sbp.sbp_partition_batch(dgs, kw)
+        sbp.sbp_tune("engine_dense_max_c", 0)
+        sparse = sbp.sbp_partition_batch(dgs, kw)
+    finally:
+        sbp.sbp_tune("engine_dense_max_c", 64)
+    for a, b in zip(dense, sparse):
+        assert a["C"] == b["C"] and a["dl"] == b["dl"]
+        assert np.array_equal(a["lab"], b["lab"])
+        assert np.array_equal(a["trace"], b["trace"])
+
+
 def test_batch_matches_oracle():
     graphs = [gen.batch_graph(n, seed=3100 + i) for i, n in enumerate([500, 700])]
     res = sbp.sbp_partition_batch([sbp.DeviceGraph(g) for g in graphs], [dict(seed=7), dict(seed=8)])
