@@ -78,6 +78,12 @@ def lib():
         L.orc_partition.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, ct.c_void_p, ct.c_int,
                                     ct.POINTER(_Params), I32P, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double),
                                     I64P, F64P, ct.c_int, ct.POINTER(ct.c_int)]
+        U8P = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.orc_induced.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, U8P, I32P, I32P, I32P, I32P, I32P,
+                                  ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+        L.orc_combine_choice.argtypes = [ct.c_int, I32P, I32P, I32P, ct.c_int, ct.c_int, I32P]
+        L.orc_dcsbp.argtypes = [ct.c_int, I32P, I32P, I32P, I32P, ct.c_int, ct.POINTER(_Params), I32P,
+                                ct.POINTER(ct.c_int), ct.POINTER(ct.c_double), I32P]
     return _lib
 
 
@@ -222,7 +228,7 @@ class Golden:
 
 # ---------------------------------------------------------------- whole method
 DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, t_pre=5e-4, t_post=1e-4,
-                merge_rate=0.5, n_batches=1, max_iters=200)
+                merge_rate=0.5, n_batches=4, max_iters=200)
 
 
 def partition(g, lab_in=None, C_in=0, trace_cap=256, **kw):
@@ -243,3 +249,48 @@ def partition(g, lab_in=None, C_in=0, trace_cap=256, **kw):
         raise ValueError(f"oracle partition failed ({rc})")
     k = min(iters.value, trace_cap)
     return dict(lab=lab_out, C=C.value, dl=dl.value, trace=tr[: 5 * k].reshape(k, 5), trace_dl=trdl[:k])
+
+
+def _params(kw):
+    p = dict(DEFAULTS)
+    p.update(kw)
+    return _Params(p["seed"], p["beta"], p["eps"], p["merge_proposals"], p["max_sweeps"], p["t_pre"], p["t_post"],
+                   p["merge_rate"], p["n_batches"], p["max_iters"])
+
+
+def induced(g, keep):
+    """Induced subgraph of the vertices with keep[v] (Alg. 3's subgraphs):
+    (sub_id [n], -1 for dropped vertices; the subgraph as a Graph)."""
+    from paper_2305_18663_amd.gen import Graph
+    keep = np.ascontiguousarray(keep, np.uint8)
+    n, e = g.n, g.e
+    sid = np.zeros(n, np.int32)
+    op = np.zeros(n + 1, np.int32); ip = np.zeros(n + 1, np.int32)
+    oi = np.zeros(e + 1, np.int32); ii = np.zeros(e + 1, np.int32)
+    ns = ct.c_int(); es = ct.c_int()
+    if lib().orc_induced(n, g.out_ptr, g.out_idx, g.in_ptr, g.in_idx, keep, sid, op, oi, ip, ii, ct.byref(ns),
+                         ct.byref(es)):
+        raise ValueError("induced subgraph: CSR and CSC disagree")
+    k, m = ns.value, es.value
+    return sid, Graph(k, m, op[: k + 1].copy(), oi[:m].copy(), ip[: k + 1].copy(), ii[:m].copy())
+
+
+def combine_choice(g, lab, C1, C2):
+    """For every community C1 + c2 the community of the first result it joins."""
+    best = np.zeros(max(C2, 1), np.int32)
+    if lib().orc_combine_choice(g.n, g.out_ptr, g.out_idx, _i32(lab), C1, C2, best):
+        raise ValueError("combine: bad labels")
+    return best[:C2]
+
+
+def dcsbp(g, n_sub, **kw):
+    """Divide-and-conquer SBP (Alg. 3) over n_sub round-robin subgraphs."""
+    P = _params(kw)
+    lab = np.zeros(g.n, np.int32)
+    C = ct.c_int(); dl = ct.c_double()
+    sub_C = np.zeros(max(n_sub, 1), np.int32)
+    rc = lib().orc_dcsbp(g.n, g.out_ptr, g.out_idx, g.in_ptr, g.in_idx, n_sub, ct.byref(P), lab, ct.byref(C),
+                         ct.byref(dl), sub_C)
+    if rc:
+        raise ValueError(f"oracle dcsbp failed ({rc})")
+    return dict(lab=lab, C=C.value, dl=dl.value, sub_C=sub_C[:n_sub])

@@ -947,3 +947,150 @@ int orc_partition(int n, const int *out_ptr, const int *out_idx, const int *in_p
     free(lab); free(map); free(partner); free(dS); free(dSl);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Divide-and-conquer SBP (Sec. II-C, Alg. 3), one process.              */
+/* Readings (the paper describes the steps, not every rule):             */
+/*  - subgraph r of s keeps the vertices v with v mod s = r and the      */
+/*    edges whose two ends it keeps ("round robin sample"); kept         */
+/*    vertices are renumbered in ascending order;                        */
+/*  - subgraph r is partitioned by the whole method with seed + 1 + r;   */
+/*  - combining results P1, P2 ("merge B2 communities into B1            */
+/*    communities"): on the graph induced by the vertices of both, with  */
+/*    P2's labels after P1's, every community c of P2 joins the          */
+/*    community c1 of P1 whose merge with c changes DL least (compared   */
+/*    on floor(dS_local 2^20) as in Alg. 1, the lowest c1 on ties), all  */
+/*    choices taken against the blockmodel before any of them is        */
+/*    applied;                                                           */
+/*  - rounds pair results (0,1), (2,3), ...; an odd last one passes on;  */
+/*    rounds repeat while more than 4 results remain;                    */
+/*  - the remaining results are concatenated (labels of result k after   */
+/*    those of results 0..k-1) and the whole method continues on the     */
+/*    full graph from that assignment with the caller's seed.            */
+/* ------------------------------------------------------------------ */
+
+/* Induced subgraph of the vertices with keep[v] != 0: ids renumbered in
+ * ascending order (sub_id[v] = new id or -1), CSR then CSC; sizes in
+ * *n_sub, *e_sub.  Output arrays sized for the whole graph. */
+int orc_induced(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx,
+                const unsigned char *keep, int *sub_id, int *s_out_ptr, int *s_out_idx, int *s_in_ptr,
+                int *s_in_idx, int *n_sub, int *e_sub)
+{
+    int k = 0;
+    for (int v = 0; v < n; ++v) sub_id[v] = keep[v] ? k++ : -1;
+    int e = 0, ei = 0;
+    s_out_ptr[0] = 0;
+    s_in_ptr[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        if (!keep[v]) continue;
+        for (int j = out_ptr[v]; j < out_ptr[v + 1]; ++j)
+            if (keep[out_idx[j]]) s_out_idx[e++] = sub_id[out_idx[j]];
+        for (int j = in_ptr[v]; j < in_ptr[v + 1]; ++j)
+            if (keep[in_idx[j]]) s_in_idx[ei++] = sub_id[in_idx[j]];
+        s_out_ptr[sub_id[v] + 1] = e;
+        s_in_ptr[sub_id[v] + 1] = ei;
+    }
+    *n_sub = k;
+    *e_sub = e;
+    return e == ei ? 0 : -1;
+}
+
+/* The merge choice of combining: lab holds P1's labels [0, C1) and P2's
+ * [C1, C1 + C2) on the induced graph; best[c2] = the chosen community of P1
+ * for community C1 + c2 (or -1 when C1 = 0). */
+int orc_combine_choice(int n, const int *out_ptr, const int *out_idx, const int *lab, int C1, int C2, int *best)
+{
+    obm m;
+    if (obm_build(&m, n, out_ptr, out_idx, lab, C1 + C2)) return -1;
+    for (int c2 = 0; c2 < C2; ++c2) {
+        int b = -1;
+        int64_t bkey = INT64_MAX;
+        for (int c1 = 0; c1 < C1; ++c1) {
+            int64_t key = rank_key(-merge_delta_L(&m, C1 + c2, c1));
+            if (b < 0 || key < bkey) { b = c1; bkey = key; }
+        }
+        best[c2] = b;
+    }
+    obm_free(&m);
+    return 0;
+}
+
+typedef struct { int nv; int *vid; int *lab; int C; } opiece;  /* global ids ascending */
+
+int orc_dcsbp(int n, const int *out_ptr, const int *out_idx, const int *in_ptr, const int *in_idx, int s,
+              const opart_params *p, int *lab_out, int *C_out, double *dl_out, int *sub_C)
+{
+    if (n < 1 || s < 1 || s > n) return -1;
+    const int e = out_ptr[n];
+    unsigned char *keep = (unsigned char *)malloc((size_t)n);
+    int *sid = (int *)malloc(sizeof(int) * (size_t)n);
+    int *sop = (int *)malloc(sizeof(int) * ((size_t)n + 1)), *sip = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *soi = (int *)malloc(sizeof(int) * ((size_t)e + 1)), *sii = (int *)malloc(sizeof(int) * ((size_t)e + 1));
+    int *slab = (int *)malloc(sizeof(int) * (size_t)n);
+    opiece *R = (opiece *)calloc((size_t)s, sizeof(opiece));
+    int nR = s, rc = 0;
+    /* 1: every subgraph partitioned on its own */
+    for (int r = 0; r < s && !rc; ++r) {
+        for (int v = 0; v < n; ++v) keep[v] = (v % s) == r;
+        int ns, es;
+        if ((rc = orc_induced(n, out_ptr, out_idx, in_ptr, in_idx, keep, sid, sop, soi, sip, sii, &ns, &es))) break;
+        opart_params q = *p;
+        q.seed = p->seed + 1 + (uint64_t)r;
+        int C;
+        double dl;
+        if ((rc = orc_partition(ns, sop, soi, sip, sii, NULL, 0, &q, slab, &C, &dl, NULL, NULL, 0, NULL))) break;
+        R[r].nv = ns;
+        R[r].vid = (int *)malloc(sizeof(int) * (size_t)ns);
+        R[r].lab = (int *)malloc(sizeof(int) * (size_t)ns);
+        for (int v = 0, i = 0; v < n; ++v)
+            if (keep[v]) { R[r].vid[i] = v; R[r].lab[i] = slab[i]; ++i; }
+        R[r].C = C;
+        if (sub_C) sub_C[r] = C;
+    }
+    /* 2: pairwise combination while more than 4 results remain */
+    int *glab = (int *)malloc(sizeof(int) * (size_t)n);
+    while (!rc && nR > 4) {
+        int k = 0;
+        for (int i = 0; i < nR; i += 2) {
+            if (i + 1 == nR) { R[k++] = R[i]; break; }
+            opiece *a = &R[i], *b = &R[i + 1];
+            memset(keep, 0, (size_t)n);
+            for (int j = 0; j < a->nv; ++j) { keep[a->vid[j]] = 1; glab[a->vid[j]] = a->lab[j]; }
+            for (int j = 0; j < b->nv; ++j) { keep[b->vid[j]] = 1; glab[b->vid[j]] = a->C + b->lab[j]; }
+            int ns, es;
+            if ((rc = orc_induced(n, out_ptr, out_idx, in_ptr, in_idx, keep, sid, sop, soi, sip, sii, &ns, &es))) break;
+            for (int v = 0; v < n; ++v)
+                if (keep[v]) slab[sid[v]] = glab[v];
+            int *best = (int *)malloc(sizeof(int) * ((size_t)b->C + 1));
+            if ((rc = orc_combine_choice(ns, sop, soi, slab, a->C, b->C, best))) { free(best); break; }
+            opiece m;
+            m.nv = ns;
+            m.vid = (int *)malloc(sizeof(int) * (size_t)ns);
+            m.lab = (int *)malloc(sizeof(int) * (size_t)ns);
+            for (int v = 0; v < n; ++v) {
+                if (!keep[v]) continue;
+                const int x = slab[sid[v]];
+                m.vid[sid[v]] = v;
+                m.lab[sid[v]] = x < a->C ? x : best[x - a->C];
+            }
+            m.C = compact_labels(ns, m.lab, a->C);
+            free(best);
+            free(a->vid); free(a->lab); free(b->vid); free(b->lab);
+            R[k++] = m;
+        }
+        nR = k;
+    }
+    /* 3: concatenation, then the whole method on the full graph */
+    if (!rc) {
+        int off = 0;
+        for (int i = 0; i < nR; ++i) {
+            for (int j = 0; j < R[i].nv; ++j) glab[R[i].vid[j]] = off + R[i].lab[j];
+            off += R[i].C;
+        }
+        rc = orc_partition(n, out_ptr, out_idx, in_ptr, in_idx, glab, off, p, lab_out, C_out, dl_out, NULL, NULL,
+                           0, NULL);
+    }
+    for (int i = 0; i < nR; ++i) { free(R[i].vid); free(R[i].lab); }
+    free(R); free(glab); free(keep); free(sid); free(sop); free(sip); free(soi); free(sii); free(slab);
+    return rc;
+}

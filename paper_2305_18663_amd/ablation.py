@@ -106,9 +106,11 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--families", default="")
     ap.add_argument("--json", default="")
+    ap.add_argument("--n-batches", type=int, default=None, help="batches per sweep (default: the partition default)")
     args = ap.parse_args()
     names = [x for x in args.families.split(",") if x] or None
-    rows, wall = run(names, seeds=range(args.seeds), scale=args.scale)
+    kw = {} if args.n_batches is None else dict(n_batches=args.n_batches)
+    rows, wall = run(names, seeds=range(args.seeds), scale=args.scale, **kw)
     summary = summarize(rows)
     print(markdown(summary), flush=True)
     print(f"{len(rows)} graphs partitioned in one batched launch: {wall:.2f} s", flush=True)

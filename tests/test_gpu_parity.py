@@ -540,7 +540,8 @@ def test_partition_easy_planted():
 
 
 def test_partition_batches_per_sweep():
-    partition_parity(gen.plain_1k(seed=55), seed=3, n_batches=4)
+    partition_parity(gen.plain_1k(seed=55), seed=3, n_batches=1)
+    partition_parity(gen.plain_1k(seed=56), seed=3, n_batches=7)
 
 
 def test_partition_from_given_assignment():

@@ -601,7 +601,8 @@ def _composed_partition(g, max_iters, **kw):
         dl_prev = O.description_length(g, lab, C1)
         sweeps = 0
         while sweeps < p["max_sweeps"]:
-            lab = O.nodal_sweep(g, lab, C1, p["seed"], sweep, beta=p["beta"], eps=p["eps"])["lab"]
+            lab = O.nodal_sweep(g, lab, C1, p["seed"], sweep, beta=p["beta"], eps=p["eps"],
+                                n_batches=p["n_batches"])["lab"]
             sweep += 1
             sweeps += 1
             dl = O.description_length(g, lab, C1)
@@ -616,7 +617,7 @@ def _composed_partition(g, max_iters, **kw):
 
 
 @pytest.mark.parametrize("kw", [dict(t_pre=5e-4, t_post=1e-4), dict(t_pre=1e-2, t_post=3e-3, max_sweeps=6),
-                                dict(t_pre=0.0, t_post=0.0, max_sweeps=3)])
+                                dict(t_pre=0.0, t_post=0.0, max_sweeps=3), dict(t_pre=5e-4, t_post=1e-4, n_batches=1)])
 def test_partition_equals_composition_of_pinned_steps(kw):
     g = gen.dcsbm([40] * 5, 1600, 4.0, seed=77, kmax=20)
     lab, C, dl, trace = _composed_partition(g, 200, seed=5, **kw)
@@ -838,3 +839,106 @@ def test_hybrid_hubs_see_the_moves_before_them(gi):
         assert r["dS"][v] == pytest.approx(O.description_length(g, moved, C) - before, rel=1e-9, abs=1e-9)
     changed = r["lab"] != cur
     assert np.array_equal(np.nonzero(changed)[0], np.array(sorted(v for v in range(g.n) if v not in hubs and r["acc"][v])))
+
+
+# ---------------------------------------------------------------- divide and conquer (Alg. 3)
+def _induced_brute(g, keep):
+    ids = np.flatnonzero(keep)
+    new = {int(v): i for i, v in enumerate(ids)}
+    src, dst = g.edges()
+    es = [(new[int(u)], new[int(w)]) for u, w in zip(src, dst) if keep[u] and keep[w]]
+    return len(ids), sorted(es)
+
+
+def test_induced_subgraph_matches_brute_force():
+    rng = np.random.default_rng(11)
+    for seed in range(4):
+        g = gen.random_multigraph(60, 400, seed=seed)
+        keep = rng.random(g.n) < 0.6
+        sid, sub = O.induced(g, keep)
+        n_ref, e_ref = _induced_brute(g, keep)
+        assert sub.n == n_ref and sub.e == len(e_ref)
+        s2, d2 = sub.edges()
+        assert sorted(zip(s2.tolist(), d2.tolist())) == e_ref
+        # CSC holds the same edges, ascending within every column
+        for w in range(sub.n):
+            col = sub.in_idx[sub.in_ptr[w]:sub.in_ptr[w + 1]]
+            assert np.all(np.diff(col) >= 0)
+            assert sorted(col.tolist()) == sorted(u for u, x in e_ref if x == w)
+        assert np.array_equal(sid[keep], np.arange(sub.n)) and np.all(sid[~keep] == -1)
+
+
+def test_combine_choice_is_the_least_full_dl_merge():
+    # every community of the second result joins the community of the first
+    # whose merge gives the smallest DL, recomputed from scratch
+    for seed in range(3):
+        g = gen.random_multigraph(50, 300, seed=20 + seed)
+        rng = np.random.default_rng(seed)
+        C1, C2 = 4, 3
+        lab = np.where(rng.random(g.n) < 0.5, rng.integers(0, C1, g.n), C1 + rng.integers(0, C2, g.n)).astype(np.int32)
+        lab[:C1] = np.arange(C1)
+        lab[C1:C1 + C2] = C1 + np.arange(C2)
+        best = O.combine_choice(g, lab, C1, C2)
+        for c2 in range(C2):
+            dls = []
+            for c1 in range(C1):
+                l2 = lab.copy()
+                l2[l2 == C1 + c2] = c1
+                dls.append(O.description_length(g, l2, C1 + C2))
+            assert dls[best[c2]] <= min(dls) + 1e-6 * abs(min(dls))
+            # the lowest community among equal (quantised) scores
+            assert best[c2] == min(c for c in range(C1) if dls[c] <= min(dls) + 1e-9 * abs(min(dls)))
+
+
+def _dcsbp_composed(g, s, **kw):
+    """Alg. 3 composed in the test from pinned oracle pieces."""
+    pieces = []
+    for r in range(s):
+        keep = (np.arange(g.n) % s) == r
+        _, sub = O.induced(g, keep)
+        kr = dict(kw)
+        kr["seed"] = kw["seed"] + 1 + r
+        res = O.partition(sub, **kr)
+        pieces.append((np.flatnonzero(keep), res["lab"].copy(), res["C"]))
+    while len(pieces) > 4:
+        nxt = []
+        for i in range(0, len(pieces), 2):
+            if i + 1 == len(pieces):
+                nxt.append(pieces[i])
+                break
+            (va, la, Ca), (vb, lb, Cb) = pieces[i], pieces[i + 1]
+            keep = np.zeros(g.n, bool)
+            keep[va] = True
+            keep[vb] = True
+            glab = np.zeros(g.n, np.int32)
+            glab[va] = la
+            glab[vb] = Ca + lb
+            sid, sub = O.induced(g, keep)
+            ids = np.flatnonzero(keep)
+            slab = glab[ids]
+            best = O.combine_choice(sub, slab, Ca, Cb)
+            merged = np.where(slab < Ca, slab, best[np.maximum(slab - Ca, 0)]).astype(np.int32)
+            C, merged = O.compact(merged, Ca)
+            nxt.append((ids, merged, C))
+        pieces = nxt
+    glab = np.zeros(g.n, np.int32)
+    off = 0
+    for v, l, C in pieces:
+        glab[v] = off + l
+        off += C
+    return O.partition(g, lab_in=glab, C_in=off, **kw)
+
+
+@pytest.mark.parametrize("s", [1, 2, 5, 9])
+def test_dcsbp_equals_composition_of_pinned_steps(s):
+    g = gen.dcsbm([30] * 6, 1500, 4.0, seed=88, kmax=20)
+    ref = _dcsbp_composed(g, s, seed=9)
+    got = O.dcsbp(g, s, seed=9)
+    assert got["C"] == ref["C"] and np.array_equal(got["lab"], ref["lab"]) and got["dl"] == ref["dl"]
+
+
+def test_dcsbp_recovers_an_easy_planted_partition():
+    g = gen.dcsbm([100] * 6, 12000, 5.0, seed=31, kmin=10, kmax=100)
+    res = O.dcsbp(g, 2, seed=12)
+    from paper_2305_18663_amd import ablation
+    assert ablation.nmi(res["lab"], g.planted) > 0.9
