@@ -333,6 +333,32 @@ int sbp_partition_batch(int32_t n_graphs, const sbp_graph *graphs /*[host]*/,
  * removed once read.  Returns the number of rows written (0 if none). */
 int sbp_partition_trace(int64_t tag, int64_t *rows /*[host] 5*cap*/, double *dl /*[host] cap*/, int32_t cap);
 
+/* ------------------------------------------------------------------ */
+/* Divide-and-conquer SBP (Sec. II-C, Alg. 3)                          */
+/* ------------------------------------------------------------------ */
+/* The vertices are split round robin into n_sub subgraphs (vertex v goes to
+ * subgraph v mod n_sub; a subgraph keeps the edges between its own
+ * vertices, renumbered in ascending order).  Every subgraph is partitioned
+ * by the whole method (as sbp_partition, with seed p->seed + 1 + r for
+ * subgraph r), all in one batched run.  While more than four partial
+ * results remain they are combined in pairs (0,1), (2,3), ... (an odd last
+ * one passes on): on the graph the pair's vertices induce, with the second
+ * result's labels after the first's, every community of the second joins
+ * the community of the first whose merge changes DL least (compared on
+ * floor(dS_local 2^20) as in sbp_merge_scores, the lowest on ties), all
+ * choices made before any is applied; the result is compacted.  The
+ * remaining results are concatenated (labels of result k after those of
+ * results 0..k-1) and the whole method continues on the full graph from that
+ * assignment with p (as sbp_partition with assign_in).
+ * Outputs: assign_out [n] (device), *C_out, *dl_out [host]; sub_C [host,
+ * nullable] receives the block count found for each subgraph [n_sub].
+ * 1 <= n_sub <= n, else SBP_E_ARG.  Workspace: sbp_dcsbp_workspace_bytes.
+ * SYNC. */
+size_t sbp_dcsbp_workspace_bytes(int32_t n, int32_t e, int32_t n_sub);
+int sbp_dcsbp(const sbp_graph *g /*[host]*/, int32_t n_sub, const sbp_partition_params *p /*[host]*/,
+              int32_t *assign_out, int32_t *C_out /*[host]*/, double *dl_out /*[host]*/, int32_t *sub_C /*[host]*/,
+              void *ws, size_t ws_bytes, void *stream);
+
 /* Continuous batching engine.  Graphs are admitted while their footprint
  * fits the engine's workspace; every sbp_engine_step advances each admitted
  * graph by one step of its own partition (a merge phase, one sweep batch,

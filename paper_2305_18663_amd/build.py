@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbp.so")
-SOURCES = ["sbp_prims.hip", "sbp_sparse.hip", "sbp_dense.hip", "sbp_engine.hip"]
+SOURCES = ["sbp_prims.hip", "sbp_sparse.hip", "sbp_dense.hip", "sbp_engine.hip", "sbp_dcsbp.hip"]
 ARCH = os.environ.get("SBP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          # packed FP32 instructions are kept out of every kernel

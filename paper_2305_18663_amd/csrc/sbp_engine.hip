@@ -579,6 +579,26 @@ void dense_scratch_of(const SingleWS &w, DenseScratch &ds, HubScratch &hs) {
     hs.hubrank = w.hub;          // [n]
 }
 
+}  // namespace
+
+size_t sparse_one_bytes(int n, int e) { return single_layout(nullptr, 0, n, e).bytes; }
+
+int build_sparse_one(const GDev &d0, void *ws, size_t ws_bytes, SparseBM &out, hipStream_t s) {
+    SingleWS w = single_layout(ws, ws_bytes, d0.n, d0.e);
+    if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
+    std::vector<GDev> hG{d0};
+    hG[0].action = ACT_NONE;
+    HostMeta hm;
+    plan_step(hG, hm);
+    int rc;
+    if ((rc = upload_step(hG, hm, w.u, s))) return rc;
+    out = w.u.bm;
+    out.Ctot = d0.C;
+    return build_union_sparse(w.u.dG, hm.m, out, w.u.ws, s);
+}
+
+namespace {
+
 // ---------------------------------------------------------------- allocation-free sweep
 // Scratch of sbp_nodal_sweep_static, a file-scope device array: the decision
 // of every vertex (an int each, SBP_STATIC_MAX_VERTICES of them), the

@@ -149,6 +149,11 @@ int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream
 // lab[v] <- map[blkstart[g] + lab[v]] for the vertex items of vstart.
 int union_relabel(const GDev *dG, int G, const int *vstart, int n_vitems, const int *blkstart, const int *map,
                   hipStream_t s);
+// Divide-and-conquer combination choice (best[c2] for every community C1 + c2).
+int union_combine_choice(const SparseBM &bm, int C1, int C2, int *best, hipStream_t s);
+// Sparse blockmodel of one graph for C labels, built in a single-graph workspace.
+size_t sparse_one_bytes(int n, int e);
+int build_sparse_one(const GDev &d, void *ws, size_t ws_bytes, SparseBM &out, hipStream_t s);
 size_t hub_scratch_ints_per_slot();
 int graph_from_edges(int n, long long e, const int *src, const int *dst, int *out_ptr, int *out_idx, int *in_ptr,
                      int *in_idx, UnionScratch &ws, long long *count, int *flag, hipStream_t s);

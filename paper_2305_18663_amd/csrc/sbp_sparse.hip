@@ -1262,6 +1262,27 @@ __device__ double merge_dL(const SparseBM &bm, int A, int B) {
     return wave_sum(acc);
 }
 
+// Divide-and-conquer combination (Alg. 3): for every community C1 + c2 the
+// community c1 < C1 of the first result whose merge with it has the smallest
+// floor(dS_local 2^20) (dS_local = -(change of L), as for Alg. 1), the lowest
+// c1 on ties.  A wave per c2, the candidates c1 in ascending order.
+__global__ void __launch_bounds__(BLK) k_combine_choice(SparseBM bm, int C1, int C2, int *__restrict__ best) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int c2 = gw; c2 < C2; c2 += nw) {
+        int b = -1;
+        long long bk = INT64_MAX;
+        for (int c1 = 0; c1 < C1; ++c1) {
+            const long long key = merge_rank(-merge_dL(bm, C1 + c2, c1));
+            if (b < 0 || key < bk) {
+                b = c1;
+                bk = key;
+            }
+        }
+        if (lane == 0) best[c2] = b;
+    }
+}
+
 // Row A and column A of M staged in LDS for the merge proposals of block A
 // (at most MERGE_ROW entries each); lds_find reads the entry at index b of a
 // staged list (0 where absent).
@@ -1683,6 +1704,14 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     }
     hipLaunchKernelGGL(k_sweep_apply, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G,
                        (int)m.Ntot, ws.nb);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_combine_choice(const SparseBM &bm, int C1, int C2, int *best, hipStream_t s) {
+    if (C2 <= 0) return 0;
+    hipLaunchKernelGGL(k_combine_choice, dim3(grid_for((long long)C2 * 64, BLK, 16384)), dim3(BLK), 0, s, bm, C1, C2,
+                       best);
     SBP_LAUNCH_CHECK();
     return 0;
 }

@@ -92,6 +92,10 @@ _SIGS = {
                                           ct.c_size_t, ct.POINTER(ct.c_void_p)]),
     "sbp_sweep_graph_launch": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "sbp_sweep_graph_destroy": (ct.c_int, [ct.c_void_p]),
+    "sbp_dcsbp_workspace_bytes": (ct.c_size_t, [ct.c_int32, ct.c_int32, ct.c_int32]),
+    "sbp_dcsbp": (ct.c_int, [ct.POINTER(Graph), ct.c_int32, ct.POINTER(PartitionParams), ct.c_void_p,
+                             ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                             ct.c_void_p]),
     "sbp_merge_scores": (ct.c_int, [ct.POINTER(Graph), ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(MergeParams),
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "sbp_merge_apply": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p,
@@ -417,6 +421,21 @@ def sbp_partition_batch(dgs, param_list=None, **kw):
         tr, trdl = sbp_partition_trace(i)
         res.append(dict(lab=outs[i].cpu().numpy(), C=C[i], dl=dl[i], trace=tr, trace_dl=trdl))
     return res
+
+
+def sbp_dcsbp(dg: DeviceGraph, n_sub, **kw):
+    """Divide-and-conquer SBP (Alg. 3) over n_sub round-robin subgraphs."""
+    p = params(**kw)
+    ws = _buffer(lib().sbp_dcsbp_workspace_bytes(dg.n, dg.e, n_sub), dg.device)
+    out = torch.empty(dg.n, dtype=torch.int32, device=dg.device)
+    C = ct.c_int32()
+    dl = ct.c_double()
+    sub_C = (ct.c_int32 * max(int(n_sub), 1))()
+    _check(lib().sbp_dcsbp(ct.byref(dg.struct), int(n_sub), ct.byref(p), _ptr(out), ct.byref(C), ct.byref(dl),
+                           ct.cast(sub_C, ct.c_void_p), _ptr(ws), ws.numel(), _stream()))
+    trace, trace_dl = sbp_partition_trace(-1)  # the final whole-graph run
+    return dict(lab=out.cpu().numpy(), C=C.value, dl=dl.value, sub_C=np.array(sub_C[:n_sub], np.int32),
+                trace=trace, trace_dl=trace_dl)
 
 
 def sbp_tune(key, value):
