@@ -88,8 +88,11 @@ typedef struct sbp_sweep_params {
                          * move one at a time in that order, each evaluated
                          * against the state the previous ones left, then the
                          * others in the n_batches snapshot batches.  0 = all
-                         * asynchronous; 0..min(n, 4096); dense tier only
-                         * (C <= SBP_DENSE_MAX_C), else SBP_E_ARG. */
+                         * asynchronous; 0..min(n, 4096), else SBP_E_ARG.  The
+                         * dense tier runs the hubs in one workgroup; the
+                         * sparse tier (C > 64) takes each hub as a batch of its
+                         * own with a blockmodel rebuild in between (slow: about
+                         * one rebuild per hub). */
 } sbp_sweep_params;
 
 /* Sweep totals, written to device memory. */
@@ -133,7 +136,8 @@ typedef struct sbp_partition_params {
     double t_post;            /* ... and after */
     double merge_rate;        /* fraction of blocks merged before the bracket exists */
     int32_t max_iters;        /* cap on merge+MCMC iterations */
-    int32_t reserved;
+    int32_t n_hubs;           /* hybrid sweeps: the n_hubs highest-degree vertices move one at a time
+                                 first in every sweep (as sbp_sweep_params.n_hubs; clamped to n) */
 } sbp_partition_params;
 
 /* ------------------------------------------------------------------ */

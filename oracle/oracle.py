@@ -39,7 +39,7 @@ class _Params(ct.Structure):
     _fields_ = [("seed", ct.c_uint64), ("beta", ct.c_double), ("eps", ct.c_int64),
                 ("merge_proposals", ct.c_int), ("max_sweeps", ct.c_int),
                 ("t_pre", ct.c_double), ("t_post", ct.c_double), ("merge_rate", ct.c_double),
-                ("n_batches", ct.c_int), ("max_iters", ct.c_int)]
+                ("n_batches", ct.c_int), ("max_iters", ct.c_int), ("n_hubs", ct.c_int)]
 
 
 _lib = None
@@ -228,14 +228,14 @@ class Golden:
 
 # ---------------------------------------------------------------- whole method
 DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, t_pre=5e-4, t_post=1e-4,
-                merge_rate=0.5, n_batches=4, max_iters=200)
+                merge_rate=0.5, n_batches=4, max_iters=200, n_hubs=0)
 
 
 def partition(g, lab_in=None, C_in=0, trace_cap=256, **kw):
     p = dict(DEFAULTS)
     p.update(kw)
     P = _Params(p["seed"], p["beta"], p["eps"], p["merge_proposals"], p["max_sweeps"], p["t_pre"], p["t_post"],
-                p["merge_rate"], p["n_batches"], p["max_iters"])
+                p["merge_rate"], p["n_batches"], p["max_iters"], p["n_hubs"])
     lab_out = np.zeros(g.n, np.int32)
     C = ct.c_int(); dl = ct.c_double(); iters = ct.c_int()
     tr = np.zeros(5 * trace_cap, np.int64); trdl = np.zeros(trace_cap)
@@ -255,7 +255,7 @@ def _params(kw):
     p = dict(DEFAULTS)
     p.update(kw)
     return _Params(p["seed"], p["beta"], p["eps"], p["merge_proposals"], p["max_sweeps"], p["t_pre"], p["t_post"],
-                   p["merge_rate"], p["n_batches"], p["max_iters"])
+                   p["merge_rate"], p["n_batches"], p["max_iters"], p["n_hubs"])
 
 
 def induced(g, keep):

@@ -846,6 +846,7 @@ typedef struct {
     double merge_rate;
     int n_batches;
     int max_iters;
+    int n_hubs;  /* hybrid sweeps (R21): hubs moved one at a time first; 0 = none */
 } opart_params;
 
 /* One MCMC phase (Alg. 2 outer loop) at C blocks: sweeps until
@@ -859,8 +860,9 @@ static int mcmc_phase(int n, const int *out_ptr, const int *out_idx, const int *
     double dl = dl_prev;
     int sweeps = 0;
     while (sweeps < p->max_sweeps) {
-        orc_nodal_sweep(n, out_ptr, out_idx, in_ptr, in_idx, lab, C, p->seed, (*sweep_ctr)++, p->beta, p->eps,
-                        p->n_batches, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
+        orc_nodal_sweep_h(n, out_ptr, out_idx, in_ptr, in_idx, lab, C, p->seed, (*sweep_ctr)++, p->beta, p->eps,
+                          p->n_batches, p->n_hubs < n ? p->n_hubs : n, NULL, NULL, NULL, NULL, NULL, NULL, NULL,
+                          NULL, NULL);
         ++sweeps;
         dl = orc_description_length(n, out_ptr, out_idx, lab, C);
         int stop = fabs(dl_prev - dl) < tol * dl;

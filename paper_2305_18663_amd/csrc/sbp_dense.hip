@@ -1919,6 +1919,7 @@ int dense_multi_sweep(const std::vector<DenseSweepJob> &jobs, const SparseBM &bm
         a.batch = g.batch;
         a.n_batches = g.n_batches;
         a.eps = g.eps;
+        a.hubrank = g.skip;
         hA[k] = a;
         hJ[k] = ToDense{g.boff, g.C, j.M, j.fM, j.dout, j.din};
     }

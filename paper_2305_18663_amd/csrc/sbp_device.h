@@ -162,8 +162,15 @@ struct GDev {
     // nullable: the sweep index is read from here instead of `sweep` (a
     // replayed graph), and the last batch's final step adds one to it
     unsigned *sweep_dev;
+    // nullable: vertices with skip[v] > 0 (the hubs a hybrid sweep already
+    // moved one at a time) take no part in this batch
+    const int *skip;
 };
 __device__ __forceinline__ unsigned sweep_of(const GDev &g) { return g.sweep_dev ? *g.sweep_dev : g.sweep; }
+// Whether vertex v belongs to this step's batch.
+__device__ __forceinline__ bool in_batch(const GDev &g, int v) {
+    return (v % g.n_batches) == g.batch && !(g.skip && g.skip[v] > 0);
+}
 
 // Per-step flat work lists: starts[g] is graph g's first item (graphs with
 // no items in a list get an empty range at the right place).

@@ -133,7 +133,8 @@ __global__ void k_hub_list(const int *__restrict__ optr, const int *__restrict__
 // split of the batch's vertices, then one workgroup adds them in order
 __global__ void __launch_bounds__(256) k_sweep_stats_part(const signed char *__restrict__ status,
                                                          const double *__restrict__ dS, int n, int batch,
-                                                         int n_batches, long long *__restrict__ part,
+                                                         int n_batches, const int *__restrict__ skip,
+                                                         long long *__restrict__ part,
                                                          double *__restrict__ sum_part) {
     __shared__ long long a[4], b[4], c[4];
     __shared__ double d[4];
@@ -142,6 +143,7 @@ __global__ void __launch_bounds__(256) k_sweep_stats_part(const signed char *__r
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x;; i += (long long)gridDim.x * 256) {
         const long long v = batch + n_batches * i;
         if (v >= n) break;
+        if (skip && skip[v] > 0) continue;  // a hub, moved before the batches
         ++np;
         const int x = status[v];
         if (x < 0) ++ns;
@@ -678,6 +680,12 @@ struct GraphRun {
     double slotDL[3] = {0, 0, 0};
     int *hub = nullptr;
     int n_hub = 0;
+    // hybrid sweeps (R21): the nh highest-degree vertices, in the order they
+    // move; hub_rank[v] = position + 1 for them, 0 otherwise (device)
+    int nh = 0;
+    std::vector<int> hub_order;
+    int *hub_rank = nullptr;
+    int hub_i = -1;  // the hub of this step, or -1 during the batches
     size_t pool_off = 0, pool_bytes = 0;
     int eslot = 0;  // engine slot (index into Cdev)
     int C = 0;
@@ -723,13 +731,15 @@ struct sbp_sweep_graph {
 namespace sbp {
 namespace {
 
+// Per-graph pool region: the three golden-search assignments, the hybrid
+// sweep's hub ranks [n] and the list of vertices above SBP_LEAF_MAX ends.
 size_t graph_bytes(int n, int e) {
     const long long hubs = 2LL * e / (SBP_LEAF_MAX + 1) + 2;
-    return 3 * al((size_t)n * 4) + al((size_t)hubs * 4);
+    return 4 * al((size_t)n * 4) + al((size_t)hubs * 4);
 }
 
 size_t pool_bound(long long V, long long E, int G) {
-    return 12 * (size_t)V + 4 * (size_t)(2 * E / (SBP_LEAF_MAX + 1)) + (size_t)G * (4 * 256 + 64);
+    return 16 * (size_t)V + 4 * (size_t)(2 * E / (SBP_LEAF_MAX + 1)) + (size_t)G * (5 * 256 + 64);
 }
 
 bool pool_alloc(sbp_engine *eng, size_t bytes, size_t &off) {
@@ -864,12 +874,21 @@ void advance(sbp_engine *eng, GraphRun &r, double dl, int C) {
             store_result(eng, r, dl);
             plan_next();
         } else {
+            r.hub_i = r.nh > 0 ? 0 : -1;  // a hybrid sweep starts with its hubs
             r.action = ACT_SWEEP;
             r.phase = GraphRun::MCMC;
         }
         break;
     case GraphRun::MCMC: {
         const int nb = std::max(1, std::min(r.p.n_batches, r.g.n));
+        if (r.hub_i >= 0) {  // the next hub, else the first batch
+            if (++r.hub_i >= r.nh) {
+                r.hub_i = -1;
+                r.batch = 0;
+            }
+            r.action = ACT_SWEEP;
+            break;
+        }
         if (r.batch + 1 < nb) {
             ++r.batch;
             r.action = ACT_SWEEP;
@@ -886,6 +905,7 @@ void advance(sbp_engine *eng, GraphRun &r, double dl, int C) {
             plan_next();
         } else {
             r.batch = 0;
+            r.hub_i = r.nh > 0 ? 0 : -1;
             r.action = ACT_SWEEP;
         }
         break;
@@ -910,6 +930,12 @@ GDev desc_of(const GraphRun &r) {
     d.eps = r.p.eps;
     d.n_batches = std::max(1, std::min(r.p.n_batches, r.g.n));
     d.batch = r.batch;
+    if (r.hub_i >= 0) {  // a hub alone: the batch {v : v mod n = hub}
+        d.n_batches = r.g.n;
+        d.batch = r.hub_order[r.hub_i];
+    } else if (r.nh > 0) {
+        d.skip = r.hub_rank;  // the batches skip the hubs
+    }
     d.sweep = r.sweep_ctr;
     d.phase = r.phase_ctr;
     d.proposals = r.p.merge_proposals;
@@ -1196,8 +1222,6 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     if ((rc = check_sweep_args(g, assign, C, bm, p))) return rc;
     BMView bv = bm_layout(bm, g->n, g->e, C);
     if (bm_bytes < bv.bytes) return fail(SBP_E_SPACE, "blockmodel storage too small");
-    if (p->n_hubs > 0 && !bv.dense)
-        return fail(SBP_E_ARG, "the sequential hub pass needs the dense tier (C <= 64)");
     SingleWS w = single_layout(ws, ws_bytes, g->n, g->e);
     if (!ws || ws_bytes < w.bytes) return fail(SBP_E_SPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
@@ -1227,23 +1251,55 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     SBP_HIP_CHECK(hipStreamSynchronize(s));
     d.hub = w.hub;
     d.n_hub = n_hub;
-    for (int b = 0; b < d.n_batches; ++b) {
-        d.batch = b;
-        std::vector<GDev> hG{d};
+    // one batch against the blockmodel of the current labels, then the rebuild
+    auto run_batch = [&](const GDev &db) -> int {
+        std::vector<GDev> hG{db};
         HostMeta hm;
         plan_step(hG, hm);
-        if ((rc = upload_step(hG, hm, w.u, s))) return rc;
+        int rc2;
+        if ((rc2 = upload_step(hG, hm, w.u, s))) return rc2;
         SparseBM sbm = bv.sp;
-        if ((rc = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, trs, s))) return rc;
-        GDev d2 = d;
+        if ((rc2 = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, trs, s))) return rc2;
+        GDev d2 = db;
         d2.action = ACT_NONE;
-        if ((rc = build_one(d2, w.u, bv, s))) return rc;
-        const int nblk = std::max(1, std::min(dense_workgroups(), (int)((g->n / d.n_batches + 255) / 256)));
+        if ((rc2 = build_one(d2, w.u, bv, s))) return rc2;
+        const int nblk = std::max(1, std::min(dense_workgroups(), (int)((g->n / db.n_batches + 255) / 256)));
         hipLaunchKernelGGL(k_sweep_stats_part, dim3(nblk), dim3(256), 0, s, (const signed char *)w.status,
-                           (const double *)trs.dS, g->n, b, d.n_batches, w.stats_part, w.sum_part);
+                           (const double *)trs.dS, g->n, db.batch, db.n_batches, db.skip, w.stats_part, w.sum_part);
         hipLaunchKernelGGL(k_sweep_stats_final, dim3(1), dim3(64), 0, s, (const long long *)w.stats_part,
                            (const double *)w.sum_part, nblk, (const double *)bv.dl, st);
         SBP_LAUNCH_CHECK();
+        return 0;
+    };
+    // hybrid sweep (R21): the hubs one at a time, each a batch of its own
+    // ({v : v mod n = hub}) against the blockmodel rebuilt after the one
+    // before; the batches then skip them (hub ranks in the dense tier's
+    // decision array, unused on this tier)
+    if (p->n_hubs > 0) {
+        std::vector<int> op(g->n + 1), ip(g->n + 1);
+        SBP_HIP_CHECK(hipMemcpyAsync(op.data(), g->out_ptr, (size_t)(g->n + 1) * 4, hipMemcpyDeviceToHost, s));
+        SBP_HIP_CHECK(hipMemcpyAsync(ip.data(), g->in_ptr, (size_t)(g->n + 1) * 4, hipMemcpyDeviceToHost, s));
+        SBP_HIP_CHECK(hipStreamSynchronize(s));
+        std::vector<int> ord(g->n), rank(g->n, 0);
+        for (int v = 0; v < g->n; ++v) ord[v] = v;
+        auto deg = [&](int v) { return (op[v + 1] - op[v]) + (ip[v + 1] - ip[v]); };
+        std::partial_sort(ord.begin(), ord.begin() + p->n_hubs, ord.end(), [&](int a, int c) {
+            return deg(a) != deg(c) ? deg(a) > deg(c) : a < c;
+        });
+        for (int i = 0; i < p->n_hubs; ++i) rank[ord[i]] = i + 1;
+        SBP_HIP_CHECK(hipMemcpyAsync(w.nb_dense, rank.data(), (size_t)g->n * 4, hipMemcpyHostToDevice, s));
+        for (int i = 0; i < p->n_hubs; ++i) {
+            GDev dh = d;
+            dh.n_batches = g->n;
+            dh.batch = ord[i];
+            if ((rc = run_batch(dh))) return rc;
+        }
+        SBP_HIP_CHECK(hipStreamSynchronize(s));  // the host rank array is released
+        d.skip = w.nb_dense;
+    }
+    for (int b = 0; b < d.n_batches; ++b) {
+        d.batch = b;
+        if ((rc = run_batch(d))) return rc;
     }
     return 0;
 }
@@ -1457,7 +1513,7 @@ int sbp_engine_admit(sbp_engine *eng, const sbp_graph *g, const sbp_partition_pa
     if (!eng || !p || !assign_out) return fail(SBP_E_ARG, "bad arguments");
     if ((rc = check_graph_args(g))) return rc;
     if (p->merge_proposals < 1 || p->eps < 0 || !(p->beta > 0) || p->n_batches < 1 || p->max_iters < 0 ||
-        !(p->merge_rate >= 0 && p->merge_rate <= 1))
+        p->n_hubs < 0 || !(p->merge_rate >= 0 && p->merge_rate <= 1))
         return fail(SBP_E_ARG, "bad partition parameters");
     if (C_init < 0 || C_init > g->n) return fail(SBP_E_ARG, "bad initial block count");
     if ((int)eng->active.size() >= eng->maxG || eng->usedV + g->n > eng->maxV || eng->usedE + g->e > eng->maxE ||
@@ -1479,7 +1535,28 @@ int sbp_engine_admit(sbp_engine *eng, const sbp_graph *g, const sbp_partition_pa
         r->slot_lab[k] = (int *)b;
         b += al((size_t)g->n * 4);
     }
+    r->hub_rank = (int *)b;
+    b += al((size_t)g->n * 4);
     r->hub = (int *)b;
+    r->nh = std::min(p->n_hubs, g->n);
+    if (r->nh > 0) {
+        // the hubs of a hybrid sweep: degree (out + in ends) descending, ties by id
+        std::vector<int> op(g->n + 1), ip(g->n + 1);
+        SBP_HIP_CHECK(hipMemcpyAsync(op.data(), g->out_ptr, (size_t)(g->n + 1) * 4, hipMemcpyDeviceToHost, s));
+        SBP_HIP_CHECK(hipMemcpyAsync(ip.data(), g->in_ptr, (size_t)(g->n + 1) * 4, hipMemcpyDeviceToHost, s));
+        SBP_HIP_CHECK(hipStreamSynchronize(s));
+        std::vector<int> ord(g->n);
+        for (int v = 0; v < g->n; ++v) ord[v] = v;
+        auto deg = [&](int v) { return (op[v + 1] - op[v]) + (ip[v + 1] - ip[v]); };
+        std::partial_sort(ord.begin(), ord.begin() + r->nh, ord.end(), [&](int a, int c) {
+            return deg(a) != deg(c) ? deg(a) > deg(c) : a < c;
+        });
+        r->hub_order.assign(ord.begin(), ord.begin() + r->nh);
+        std::vector<int> rank(g->n, 0);
+        for (int i = 0; i < r->nh; ++i) rank[r->hub_order[i]] = i + 1;
+        SBP_HIP_CHECK(hipMemcpyAsync(r->hub_rank, rank.data(), (size_t)g->n * 4, hipMemcpyHostToDevice, s));
+        SBP_HIP_CHECK(hipStreamSynchronize(s));
+    }
     // hub list (vertices with more than SBP_LEAF_MAX edge ends)
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, eng->u.hub_count, 0);
     hipLaunchKernelGGL(k_hub_list, dim3(grid_for(g->n, BLK, 4096)), dim3(BLK), 0, s, g->out_ptr, g->in_ptr, g->n,

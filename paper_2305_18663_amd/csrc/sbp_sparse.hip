@@ -357,7 +357,7 @@ __device__ __forceinline__ bool sweep_item(const GDev *G, const int *starts, int
     const GDev &d = G[g];
     const int v = i - starts[g];
     const int k = d.out_ptr[v + 1] - d.out_ptr[v] + d.in_ptr[v + 1] - d.in_ptr[v];
-    return (v % d.n_batches) == d.batch && k >= kmin && k <= kmax;
+    return in_batch(d, v) && k >= kmin && k <= kmax;
 }
 
 // s_draw by a whole wave over t's running sums [lo, hi): each round probes 64
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 tko = d.out_ptr[tv + 1] - top;
                 tip = d.in_ptr[tv];
                 tki = d.in_ptr[tv + 1] - tip;
-                tsmall = (tv % d.n_batches) == d.batch && tko + tki >= KMIN && tko + tki <= KMAX;
+                tsmall = in_batch(d, tv) && tko + tki >= KMIN && tko + tki <= KMAX;
                 if (tsmall) {
                     tr0 = d.boff + d.lab[tv];
                     trp0 = bm.rptr[tr0];
@@ -1166,7 +1166,7 @@ __global__ void __launch_bounds__(HUB_THREADS) k_sweep_hub(const GDev *__restric
         const int g = find_graph(starts, nG, item);
         const GDev &d = G[g];
         const int v = d.hub[item - starts[g]];
-        if ((v % d.n_batches) != d.batch) continue;
+        if (!in_batch(d, v)) continue;
         const int r = d.boff + d.lab[v];
         const int op = d.out_ptr[v], kout = d.out_ptr[v + 1] - op;
         const int ip = d.in_ptr[v], kin = d.in_ptr[v + 1] - ip;
@@ -1212,7 +1212,7 @@ __global__ void k_sweep_apply(const GDev *__restrict__ G, const int *__restrict_
         const GDev &d = G[g];
         if (d.action != ACT_SWEEP && d.action != ACT_DSWEEP) continue;
         const int v = i - d.voff;
-        if ((v % d.n_batches) != d.batch) continue;
+        if (!in_batch(d, v)) continue;
         const int x = nb[i];
         if (x >= 0) d.lab[v] = x;
     }

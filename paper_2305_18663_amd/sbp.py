@@ -57,7 +57,7 @@ class PartitionParams(ct.Structure):
     _fields_ = [("seed", ct.c_uint64), ("beta", ct.c_double), ("eps", ct.c_int32), ("merge_proposals", ct.c_int32),
                 ("max_sweeps", ct.c_int32), ("n_batches", ct.c_int32), ("t_pre", ct.c_double),
                 ("t_post", ct.c_double), ("merge_rate", ct.c_double), ("max_iters", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("n_hubs", ct.c_int32)]
 
 
 # Four batches per sweep in the whole method: a fully asynchronous sweep (one
@@ -65,7 +65,7 @@ class PartitionParams(ct.Structure):
 # search on dense graphs whose description length is flat at high block
 # counts; the single-sweep entry point keeps one batch as its default.
 PARTITION_DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, n_batches=4,
-                          t_pre=5e-4, t_post=1e-4, merge_rate=0.5, max_iters=200)
+                          t_pre=5e-4, t_post=1e-4, merge_rate=0.5, max_iters=200, n_hubs=0)
 
 _SIGS = {
     "sbp_last_error": (ct.c_char_p, []),
@@ -378,7 +378,7 @@ def params(**kw):
     p = dict(PARTITION_DEFAULTS)
     p.update(kw)
     return PartitionParams(p["seed"], p["beta"], p["eps"], p["merge_proposals"], p["max_sweeps"], p["n_batches"],
-                           p["t_pre"], p["t_post"], p["merge_rate"], p["max_iters"], 0)
+                           p["t_pre"], p["t_post"], p["merge_rate"], p["max_iters"], p["n_hubs"])
 
 
 def sbp_partition_trace(tag, cap=512):

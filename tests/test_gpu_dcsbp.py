@@ -52,6 +52,10 @@ def test_dcsbp_one_batch_per_sweep():
     _parity(gen.plain_1k(seed=63), 6, seed=23, n_batches=1)
 
 
+def test_dcsbp_hybrid_hubs():
+    _parity(gen.plain_1k(seed=64), 3, seed=24, n_hubs=5)
+
+
 def test_dcsbp_degenerate():
     # every subgraph a single vertex; an edgeless graph; a multigraph with self-loops
     g = gen.random_multigraph(12, 60, seed=5)

@@ -392,14 +392,28 @@ def test_sweep_hybrid_200k():
     sweep_parity(g, lab0, 45, seed=2001, sweep=0, n_hubs=16)
 
 
+@pytest.mark.parametrize("n_batches", [1, 3])
+@pytest.mark.parametrize("n_hubs", [1, 7, 40])
+@pytest.mark.parametrize("name,C", [("plain_1k", 70), ("multi_selfloops", 150)])
+def test_sweep_hybrid_hubs_sparse_tier(name, C, n_hubs, n_batches):
+    # the sparse tier: every hub a batch of its own against the rebuilt blockmodel
+    g = GRAPHS[name]()
+    lab0 = gen.initial_labels(g.n, C, seed=C + 5)
+    _, _, ref = sweep_parity(g, lab0, C, seed=33, sweep=n_hubs, n_batches=n_batches, n_hubs=n_hubs)
+    assert ref["proposals"] == g.n
+
+
+def test_sweep_hybrid_large_hubs_sparse_tier():
+    g = hub_graph()
+    lab0 = gen.initial_labels(g.n, 300, seed=41)
+    sweep_parity(g, lab0, 300, seed=44, sweep=3, n_batches=2, n_hubs=6)
+
+
 def test_sweep_hybrid_rejects():
     g = GRAPHS["plain_1k"]()
     dg = sbp.DeviceGraph(g)
     lab = sbp.labels(gen.initial_labels(g.n, 70, seed=1))
-    bm = sbp.sbp_build_blockmodel(dg, lab, 70)
     before = lab.cpu().numpy().copy()
-    with pytest.raises(sbp.SbpError):  # sparse tier (C > 64)
-        sbp.sbp_nodal_sweep(dg, lab, 70, bm, 1, 0, n_hubs=4)
     lab10 = sbp.labels(gen.initial_labels(g.n, 10, seed=1))
     bm10 = sbp.sbp_build_blockmodel(dg, lab10, 10)
     with pytest.raises(sbp.SbpError):  # more hubs than vertices
@@ -542,6 +556,31 @@ def test_partition_easy_planted():
 def test_partition_batches_per_sweep():
     partition_parity(gen.plain_1k(seed=55), seed=3, n_batches=1)
     partition_parity(gen.plain_1k(seed=56), seed=3, n_batches=7)
+
+
+@pytest.mark.parametrize("n_hubs", [1, 6, 40])
+def test_partition_hybrid_hubs(n_hubs):
+    # Hybrid SBP in the whole method: every sweep moves the n_hubs
+    # highest-degree vertices one at a time first, on both tiers as C falls
+    partition_parity(gen.plain_1k(seed=57), seed=5, n_hubs=n_hubs)
+
+
+def test_partition_hybrid_every_vertex_a_hub():
+    g = gen.dcsbm([25] * 4, 600, 4.0, seed=58, kmax=20)
+    partition_parity(g, seed=6, n_hubs=g.n + 5, n_batches=1)
+
+
+def test_batch_hybrid_equals_alone():
+    graphs = [gen.batch_graph(n, seed=3400 + i) for i, n in enumerate([600, 1300, 900])]
+    dgs = [sbp.DeviceGraph(g) for g in graphs]
+    kw = [dict(seed=70 + i, n_hubs=h) for i, h in enumerate([0, 8, 3])]
+    batch = sbp.sbp_partition_batch(dgs, kw)
+    for i, dg in enumerate(dgs):
+        alone = sbp.sbp_partition(dg, **kw[i])
+        assert batch[i]["C"] == alone["C"] and batch[i]["dl"] == alone["dl"]
+        assert np.array_equal(batch[i]["lab"], alone["lab"])
+    ora = O.partition(graphs[1], **kw[1])
+    assert batch[1]["C"] == ora["C"] and np.array_equal(batch[1]["lab"], ora["lab"])
 
 
 def test_partition_from_given_assignment():

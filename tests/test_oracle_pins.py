@@ -602,7 +602,7 @@ def _composed_partition(g, max_iters, **kw):
         sweeps = 0
         while sweeps < p["max_sweeps"]:
             lab = O.nodal_sweep(g, lab, C1, p["seed"], sweep, beta=p["beta"], eps=p["eps"],
-                                n_batches=p["n_batches"])["lab"]
+                                n_batches=p["n_batches"], n_hubs=min(p["n_hubs"], g.n))["lab"]
             sweep += 1
             sweeps += 1
             dl = O.description_length(g, lab, C1)
@@ -617,7 +617,8 @@ def _composed_partition(g, max_iters, **kw):
 
 
 @pytest.mark.parametrize("kw", [dict(t_pre=5e-4, t_post=1e-4), dict(t_pre=1e-2, t_post=3e-3, max_sweeps=6),
-                                dict(t_pre=0.0, t_post=0.0, max_sweeps=3), dict(t_pre=5e-4, t_post=1e-4, n_batches=1)])
+                                dict(t_pre=0.0, t_post=0.0, max_sweeps=3), dict(t_pre=5e-4, t_post=1e-4, n_batches=1),
+                                dict(t_pre=5e-4, t_post=1e-4, n_hubs=12), dict(t_pre=5e-4, t_post=1e-4, n_hubs=500)])
 def test_partition_equals_composition_of_pinned_steps(kw):
     g = gen.dcsbm([40] * 5, 1600, 4.0, seed=77, kmax=20)
     lab, C, dl, trace = _composed_partition(g, 200, seed=5, **kw)
