@@ -228,7 +228,7 @@ class Golden:
 
 # ---------------------------------------------------------------- whole method
 DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, t_pre=5e-4, t_post=1e-4,
-                merge_rate=0.5, n_batches=4, max_iters=200, n_hubs=0)
+                merge_rate=0.5, n_batches=2, max_iters=200, n_hubs=0)
 
 
 def partition(g, lab_in=None, C_in=0, trace_cap=256, **kw):

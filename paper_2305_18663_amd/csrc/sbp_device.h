@@ -165,6 +165,9 @@ struct GDev {
     // nullable: vertices with skip[v] > 0 (the hubs a hybrid sweep already
     // moved one at a time) take no part in this batch
     const int *skip;
+    // nullable: M of this graph as a C x C table (graph-local ids), filled
+    // for the step, so the sweep reads an entry with one load
+    int *mdense;
 };
 __device__ __forceinline__ unsigned sweep_of(const GDev &g) { return g.sweep_dev ? *g.sweep_dev : g.sweep; }
 // Whether vertex v belongs to this step's batch.

@@ -316,6 +316,9 @@ struct UnionLayout {
     unsigned ftab_max;
     char *dslots;     // per engine slot: dense M, f(M) and degrees for C <= 64
     void *dmulti;     // launch tables of the multi-graph dense sweep
+    int *tables;      // C x C lookup tables of M for the sparse sweeps of a step
+    long long table_ints;
+    int *tlist;       // [G] graphs given a table this step
     size_t bytes;
 };
 
@@ -323,6 +326,7 @@ struct UnionLayout {
 // degrees [64] + [64] ints (rows packed at the graph's own C).
 constexpr size_t DSLOT_BYTES = 64 * 64 * 4 + 64 * 64 * 8 + 2 * 64 * 4;
 int g_engine_dense_max_c = SBP_DENSE_MAX_C;  // engine sweeps at C <= this use the dense kernels (0: never)
+int g_table_max_c = SBP_TABLE_MAX_C;         // sparse sweeps at C <= this read M from a lookup table (0: never)
 
 UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     UnionLayout u{};
@@ -376,6 +380,15 @@ UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     u.ftab = a.take<double>((size_t)u.ftab_max + 1);
     u.dslots = a.take<char>(DSLOT_BYTES * (size_t)G);
     u.dmulti = a.take<char>(dense_multi_scratch_bytes(G));
+    {
+        // tables for block counts up to SBP_TABLE_MAX_C, at most 256 MB
+        const long long cmax = std::min<long long>(N, SBP_TABLE_MAX_C);
+        long long t = std::min<long long>(64LL << 20, cmax * cmax * std::max(1, std::min(G, 64)));
+        t = std::min(t, std::max<long long>(N, 1) * SBP_TABLE_MAX_C);
+        u.table_ints = std::max<long long>(t, 1);
+    }
+    u.tables = a.take<int>((size_t)u.table_ints);
+    u.tlist = a.take<int>(G);
     u.bytes = a.used;
     return u;
 }
@@ -955,17 +968,33 @@ int engine_step(sbp_engine *eng, int *active_out) {
     int rc;
     // 1-3: layout, counts, rebuild, DL
     std::vector<GDev> hG(G);
+    // lookup tables of M for the graphs whose count (an upper bound: a merge
+    // of the last step may have lowered it on the device) allows one, while
+    // the space lasts; tables change no result, only the lookups' cost
+    std::vector<int *> tab(G, nullptr);
+    std::vector<int> tlist;
+    long long tused = 0;
     for (int g = 0; g < G; ++g) {
         hG[g] = desc_of(*eng->active[g]);
         hG[g].action = ACT_NONE;
+        const long long Cb = hG[g].C;
+        if (Cb <= g_table_max_c && Cb > g_engine_dense_max_c && Cb * Cb <= u.table_ints - tused) {
+            tab[g] = u.tables + tused;
+            tused += (Cb * Cb + 63) & ~63LL;
+            hG[g].mdense = tab[g];
+            tlist.push_back(g);
+        }
     }
     HostMeta hm;
     plan_step(hG, hm);
     if ((rc = upload_step(hG, hm, u, s))) return rc;
+    if (!tlist.empty())
+        SBP_HIP_CHECK(hipMemcpyAsync(u.tlist, tlist.data(), tlist.size() * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fix_C, dim3((G + 63) / 64), dim3(64), 0, s, u.dG, G, (const int *)u.Cdev);
     SBP_LAUNCH_CHECK();
     SparseBM bm = u.bm;
     if ((rc = build_union_sparse(u.dG, hm.m, bm, u.ws, s))) return rc;
+    if ((rc = union_lookup_tables(u.dG, u.tlist, (int)tlist.size(), bm, s))) return rc;
     if ((rc = union_dl(u.dG, hm.m, bm, u.ws, s))) return rc;
     // 4: read back
     eng->h_dl.resize(G);
@@ -990,6 +1019,7 @@ int engine_step(sbp_engine *eng, int *active_out) {
         d.eoff = hG[g].eoff;
         d.C = r.C;
         if (r.action == ACT_MERGE) d.C = r.C0;
+        d.mdense = tab[g];  // filled for the count the build used, which the actions keep
         if (r.action == ACT_SWEEP && d.C <= g_engine_dense_max_c) {
             // the dense kernels evaluate it; the union kernels apply it
             d.action = ACT_DSWEEP;
@@ -1252,13 +1282,20 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
     d.hub = w.hub;
     d.n_hub = n_hub;
     // one batch against the blockmodel of the current labels, then the rebuild
-    auto run_batch = [&](const GDev &db) -> int {
+    const bool tabled = (long long)C <= g_table_max_c && (long long)C * C <= w.u.table_ints;
+    auto run_batch = [&](const GDev &db0) -> int {
+        GDev db = db0;
+        if (tabled) db.mdense = w.u.tables;
         std::vector<GDev> hG{db};
         HostMeta hm;
         plan_step(hG, hm);
         int rc2;
         if ((rc2 = upload_step(hG, hm, w.u, s))) return rc2;
         SparseBM sbm = bv.sp;
+        if (tabled) {
+            hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.u.tlist, 0);
+            if ((rc2 = union_lookup_tables(w.u.dG, w.u.tlist, 1, sbm, s))) return rc2;
+        }
         if ((rc2 = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, trs, s))) return rc2;
         GDev d2 = db;
         d2.action = ACT_NONE;
@@ -1687,6 +1724,10 @@ int sbp_tune(const char *key, int64_t value) {
     if (!key) return fail(SBP_E_ARG, "null key");
     if (!strcmp(key, "engine_dense_max_c") && value >= 0 && value <= SBP_DENSE_MAX_C) {
         g_engine_dense_max_c = (int)value;
+        return 0;
+    }
+    if (!strcmp(key, "table_max_c") && value >= 0 && value <= SBP_TABLE_MAX_C) {
+        g_table_max_c = (int)value;
         return 0;
     }
     if (dense_tune(key, (long long)value) == 0) return 0;

@@ -445,6 +445,24 @@ __device__ __forceinline__ void lists_lookup(const MoveLists &L, int nmax, int t
     for (int l = 0; l < 4; ++l) out[l] = kv[l] == t ? L.v[l][lo[l]] : 0;
 }
 
+// The four entries (M_rt, M_st, M_tr, M_ts) of a move from r to s for the
+// neighbour block t (union ids): one load each from the graph's lookup table
+// (C x C, when the step gave it one), else searches of the staged lists.
+template <int ROW>
+__device__ __forceinline__ void entries4(const GDev &d, const MoveLists &L, int nmax, int r, int s, int t,
+                                         int out[4]) {
+    if (d.mdense) {
+        const int C = d.C, rl = r - d.boff, sl = s - d.boff, tl = t - d.boff;
+        const int *__restrict__ M = d.mdense;
+        out[0] = M[rl * C + tl];
+        out[1] = M[sl * C + tl];
+        out[2] = M[tl * C + rl];
+        out[3] = M[tl * C + sl];
+    } else {
+        lists_lookup<ROW>(L, nmax, t, out);
+    }
+}
+
 // f(x) = x ln x of the integers below FT_N, built by each workgroup in LDS
 // with the same xlogx as the direct path, so both give identical values.
 constexpr int FT_N = 512;
@@ -567,8 +585,11 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
             MoveLists ML;
             ML.samp = SC[wv];
             ML.sampled = 0;
-            stage_list<LEAF_ROW>(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
-            stage_list<LEAF_ROW>(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
+            ML.n[0] = ML.n[1] = ML.n[2] = ML.n[3] = 0;
+            if (!d.mdense) {  // with a lookup table no list is needed
+                stage_list<LEAF_ROW>(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
+                stage_list<LEAF_ROW>(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
+            }
             const int dor = bm.dout[r], dir = bm.din[r];
             // proposal: the drawn end's block comes from the lane holding its key
             const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
@@ -597,7 +618,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
                 continue;
             }
             // row s and column s of M
-            {
+            if (!d.mdense) {
                 const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
                 stage_list<LEAF_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
                 stage_list<LEAF_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
@@ -681,7 +702,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
                 const int kp = ko | ki << 16;
                 const long long dtt = (long long)bm.dout[t] + bm.din[t];
                 int Mv[4];
-                lists_lookup<LEAF_ROW>(ML, nmax, t, Mv);
+                entries4<LEAF_ROW>(d, ML, nmax, r, s, t, Mv);
                 if (t == r) {
                     CV[wv][0] = Mv[0];  // M_rr
                     CV[wv][1] = Mv[1];  // M_sr
@@ -801,8 +822,11 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
             MoveLists ML;
             ML.samp = SC[gs];
             ML.sampled = 0;
-            stage_list<SMALL_ROW>(ML, 0, bm.rcol + b0r, bm.rval + b0r, b1r - b0r, SC[gs], SV[gs], gl, GS);
-            stage_list<SMALL_ROW>(ML, 2, bm.crow + c0r, bm.cval + c0r, c1r - c0r, SC[gs], SV[gs], gl, GS);
+            ML.n[0] = ML.n[1] = ML.n[2] = ML.n[3] = 0;
+            if (!d.mdense) {  // with a lookup table no list is needed
+                stage_list<SMALL_ROW>(ML, 0, bm.rcol + b0r, bm.rval + b0r, b1r - b0r, SC[gs], SV[gs], gl, GS);
+                stage_list<SMALL_ROW>(ML, 2, bm.crow + c0r, bm.cval + c0r, c1r - c0r, SC[gs], SV[gs], gl, GS);
+            }
             const int dor = bm.dout[r], dir = bm.din[r];
             // proposal; t's degree and running-sum range come in one round trip
             const Words4 W = draw_words(d.seed, (uint32_t)v, d.sweep, 0u, 0u);
@@ -861,7 +885,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 record_move(d, v, r, o, true, nb, tr);
             }
             // row s and column s of M
-            {
+            if (!d.mdense) {
                 const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
                 stage_list<SMALL_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[gs], SV[gs], gl, GS);
                 stage_list<SMALL_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[gs], SV[gs], gl, GS);
@@ -908,7 +932,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 }
                 const long long dtt = (long long)bm.dout[tt] + bm.din[tt];
                 int Mv[4];
-                lists_lookup<SMALL_ROW>(ML, nmax, tt, Mv);
+                entries4<SMALL_ROW>(d, ML, nmax, r, s, tt, Mv);
                 if (tt == r) {
                     CV[gs][0] = Mv[0];  // M_rr
                     CV[gs][1] = Mv[1];  // M_sr
@@ -1704,6 +1728,40 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     }
     hipLaunchKernelGGL(k_sweep_apply, dim3(grid_for(m.Ntot, BLK, 8192)), dim3(BLK), 0, s, dG, m.voff, m.G,
                        (int)m.Ntot, ws.nb);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+// Lookup tables of M (C x C ints, graph-local ids) for the listed graphs,
+// from the union rows: the graph's workgroups zero its table, then scatter
+// its rows (a second launch, so every zero lands first).
+__global__ void __launch_bounds__(BLK) k_table_zero(const GDev *__restrict__ G, const int *__restrict__ list,
+                                                    int n_list, int per) {
+    const GDev &d = G[list[blockIdx.x / per]];
+    const long long CC = (long long)d.C * d.C;
+    for (long long i = (long long)(blockIdx.x % per) * BLK + threadIdx.x; i < CC; i += (long long)per * BLK)
+        d.mdense[i] = 0;
+}
+__global__ void __launch_bounds__(BLK) k_table_fill(const GDev *__restrict__ G, const int *__restrict__ list,
+                                                    int n_list, int per, SparseBM bm) {
+    const GDev &d = G[list[blockIdx.x / per]];
+    const int p0 = bm.rptr[d.boff], p1 = bm.rptr[d.boff + d.C];
+    for (int q = p0 + (blockIdx.x % per) * BLK + threadIdx.x; q < p1; q += per * BLK) {
+        // the row of entry q: last block whose rows start at or before q
+        int lo = d.boff, hi = d.boff + d.C - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bm.rptr[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        d.mdense[(lo - d.boff) * d.C + (bm.rcol[q] - d.boff)] = bm.rval[q];
+    }
+}
+
+int union_lookup_tables(const GDev *dG, const int *list, int n_list, const SparseBM &bm, hipStream_t s) {
+    if (n_list <= 0) return 0;
+    constexpr int PER = 16;  // workgroups per graph
+    hipLaunchKernelGGL(k_table_zero, dim3(n_list * PER), dim3(BLK), 0, s, dG, list, n_list, PER);
+    hipLaunchKernelGGL(k_table_fill, dim3(n_list * PER), dim3(BLK), 0, s, dG, list, n_list, PER, bm);
     SBP_LAUNCH_CHECK();
     return 0;
 }

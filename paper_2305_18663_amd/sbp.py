@@ -60,11 +60,11 @@ class PartitionParams(ct.Structure):
                 ("n_hubs", ct.c_int32)]
 
 
-# Four batches per sweep in the whole method: a fully asynchronous sweep (one
+# Two batches per sweep in the whole method: a fully asynchronous sweep (one
 # batch, every vertex against the same snapshot) can stall the block-count
 # search on dense graphs whose description length is flat at high block
 # counts; the single-sweep entry point keeps one batch as its default.
-PARTITION_DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, n_batches=4,
+PARTITION_DEFAULTS = dict(seed=2000, beta=3.0, eps=1, merge_proposals=10, max_sweeps=100, n_batches=2,
                           t_pre=5e-4, t_post=1e-4, merge_rate=0.5, max_iters=200, n_hubs=0)
 
 _SIGS = {

@@ -643,6 +643,37 @@ def test_engine_dense_sweeps_equal_sparse_sweeps(n_batches):
         assert np.array_equal(a["trace"], b["trace"])
 
 
+def test_lookup_tables_change_nothing():
+    # sparse-tier sweeps read M from a C x C table when C <= 2048; with the
+    # tables switched off (binary searches of the rows) every result is equal
+    g = GRAPHS["multi_selfloops"]()
+    dg = sbp.DeviceGraph(g)
+    for C in (70, 150, 299):
+        lab0 = gen.initial_labels(g.n, C, seed=C)
+        out = []
+        for tmax in (2048, 0):
+            sbp.sbp_tune("table_max_c", tmax)
+            lab = sbp.labels(lab0)
+            bm = sbp.sbp_build_blockmodel(dg, lab, C)
+            tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, 7, C, n_batches=2)
+            out.append((lab.cpu().numpy(), tr))
+        sbp.sbp_tune("table_max_c", 2048)
+        (la, ta), (lb, tb) = out
+        assert np.array_equal(la, lb) and np.array_equal(ta["prop"], tb["prop"])
+        assert np.array_equal(ta["accept"], tb["accept"]) and np.array_equal(ta["dS"], tb["dS"])
+    graphs = [gen.batch_graph(n, seed=3500 + i) for i, n in enumerate([800, 4000, 1500])]
+    dgs = [sbp.DeviceGraph(x) for x in graphs]
+    kw = [dict(seed=90 + i) for i in range(len(graphs))]
+    try:
+        a = sbp.sbp_partition_batch(dgs, kw)
+        sbp.sbp_tune("table_max_c", 0)
+        b = sbp.sbp_partition_batch(dgs, kw)
+    finally:
+        sbp.sbp_tune("table_max_c", 2048)
+    for x, y in zip(a, b):
+        assert x["C"] == y["C"] and x["dl"] == y["dl"] and np.array_equal(x["lab"], y["lab"])
+
+
 def test_batch_matches_oracle():
     graphs = [gen.batch_graph(n, seed=3100 + i) for i, n in enumerate([500, 700])]
     res = sbp.sbp_partition_batch([sbp.DeviceGraph(g) for g in graphs], [dict(seed=7), dict(seed=8)])
