@@ -399,6 +399,13 @@ int sbp_engine_destroy(sbp_engine *eng);
  *                            most value/1024 of the vertices moved (default
  *                            128; 0..1024, or -1 for never), otherwise by a
  *                            pass over every edge end
+ *   "engine_dense_max_c"     engine sweep batches at C <= value (0..64) run on
+ *                            the dense kernels (default 64; 0 = never)
+ *   "table_max_c"            sparse sweeps at C <= value (0..2048) read M from
+ *                            a C x C lookup table (default 2048; 0 = never)
+ *   "table_build"            engine steps count M into the tables: 0 never,
+ *                            1 when the tables are small against the edges
+ *                            (default), 2 whenever every graph's table fits
  * Returns SBP_E_ARG for an unknown key or a value out of range. */
 int sbp_tune(const char *key, int64_t value);
 

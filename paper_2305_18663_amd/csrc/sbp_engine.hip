@@ -327,6 +327,7 @@ struct UnionLayout {
 constexpr size_t DSLOT_BYTES = 64 * 64 * 4 + 64 * 64 * 8 + 2 * 64 * 4;
 int g_engine_dense_max_c = SBP_DENSE_MAX_C;  // engine sweeps at C <= this use the dense kernels (0: never)
 int g_table_max_c = SBP_TABLE_MAX_C;         // sparse sweeps at C <= this read M from a lookup table (0: never)
+int g_table_build = 1;  // count M into the tables: 0 never, 1 when they are small against the edges, 2 whenever all fit
 
 UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     UnionLayout u{};
@@ -974,11 +975,27 @@ int engine_step(sbp_engine *eng, int *active_out) {
     std::vector<int *> tab(G, nullptr);
     std::vector<int> tlist;
     long long tused = 0;
+    bool all_tabled = g_table_build > 0;  // every graph gets a table: M is counted into them
+    {
+        // worth it when the tables are small against the edges: the build
+        // then scans sum C^2 entries (columns with a stride of C) instead of
+        // radix-sorting every edge's key several times
+        long long need = 0, sq = 0, edges = 0;
+        for (int g = 0; g < G && all_tabled; ++g) {
+            const long long Cb = eng->active[g]->C;
+            all_tabled = Cb <= g_table_max_c;
+            need += (Cb * Cb + 63) & ~63LL;
+            sq += Cb * Cb;
+            edges += eng->active[g]->g.e;
+        }
+        all_tabled = all_tabled && need <= u.table_ints && (g_table_build == 2 || 8 * sq <= edges);
+    }
     for (int g = 0; g < G; ++g) {
         hG[g] = desc_of(*eng->active[g]);
         hG[g].action = ACT_NONE;
         const long long Cb = hG[g].C;
-        if (Cb <= g_table_max_c && Cb > g_engine_dense_max_c && Cb * Cb <= u.table_ints - tused) {
+        if (all_tabled ||
+            (Cb <= g_table_max_c && Cb > g_engine_dense_max_c && Cb * Cb <= u.table_ints - tused)) {
             tab[g] = u.tables + tused;
             tused += (Cb * Cb + 63) & ~63LL;
             hG[g].mdense = tab[g];
@@ -993,8 +1010,12 @@ int engine_step(sbp_engine *eng, int *active_out) {
     hipLaunchKernelGGL(k_fix_C, dim3((G + 63) / 64), dim3(64), 0, s, u.dG, G, (const int *)u.Cdev);
     SBP_LAUNCH_CHECK();
     SparseBM bm = u.bm;
-    if ((rc = build_union_sparse(u.dG, hm.m, bm, u.ws, s))) return rc;
-    if ((rc = union_lookup_tables(u.dG, u.tlist, (int)tlist.size(), bm, s))) return rc;
+    if (all_tabled) {
+        if ((rc = build_union_from_tables(u.dG, hm.m, bm, u.ws, u.tlist, G, s))) return rc;
+    } else {
+        if ((rc = build_union_sparse(u.dG, hm.m, bm, u.ws, s))) return rc;
+        if ((rc = union_lookup_tables(u.dG, G, (int)tlist.size(), bm, s))) return rc;
+    }
     if ((rc = union_dl(u.dG, hm.m, bm, u.ws, s))) return rc;
     // 4: read back
     eng->h_dl.resize(G);
@@ -1292,10 +1313,7 @@ int sbp_nodal_sweep(const sbp_graph *g, int32_t *assign, int32_t C, void *bm, si
         int rc2;
         if ((rc2 = upload_step(hG, hm, w.u, s))) return rc2;
         SparseBM sbm = bv.sp;
-        if (tabled) {
-            hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.u.tlist, 0);
-            if ((rc2 = union_lookup_tables(w.u.dG, w.u.tlist, 1, sbm, s))) return rc2;
-        }
+        if (tabled && (rc2 = union_lookup_tables(w.u.dG, 1, 1, sbm, s))) return rc2;
         if ((rc2 = union_sweep(w.u.dG, hm.m, sbm, w.u.ws, trs, s))) return rc2;
         GDev d2 = db;
         d2.action = ACT_NONE;
@@ -1728,6 +1746,10 @@ int sbp_tune(const char *key, int64_t value) {
     }
     if (!strcmp(key, "table_max_c") && value >= 0 && value <= SBP_TABLE_MAX_C) {
         g_table_max_c = (int)value;
+        return 0;
+    }
+    if (!strcmp(key, "table_build") && value >= 0 && value <= 2) {
+        g_table_build = (int)value;
         return 0;
     }
     if (dense_tune(key, (long long)value) == 0) return 0;

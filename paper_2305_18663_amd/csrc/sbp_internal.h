@@ -149,10 +149,15 @@ int union_compact(const GDev *dG, const StepMeta &m, UnionScratch &ws, hipStream
 // lab[v] <- map[blkstart[g] + lab[v]] for the vertex items of vstart.
 int union_relabel(const GDev *dG, int G, const int *vstart, int n_vitems, const int *blkstart, const int *map,
                   hipStream_t s);
-// Fill the C x C lookup tables (GDev.mdense) of the listed graphs [n_list]
-// (device list of graph indices) from the union blockmodel.
-int union_lookup_tables(const GDev *dG, const int *list, int n_list, const SparseBM &bm, hipStream_t s);
+// Fill the C x C lookup tables (GDev.mdense) of the graphs that have one
+// (n_list of the nG graphs) from the union blockmodel.
+int union_lookup_tables(const GDev *dG, int nG, int n_list, const SparseBM &bm, hipStream_t s);
 constexpr int SBP_TABLE_MAX_C = 2048;  // block counts that get a lookup table
+// The union blockmodel counted into the graphs' tables (every graph of the
+// step has GDev.mdense; list [n_list] = all graph indices): the same arrays as
+// build_union_sparse, which the tables then also serve as lookups.
+int build_union_from_tables(const GDev *dG, const StepMeta &m, SparseBM &bm, UnionScratch &ws,
+                            const int *list, int n_list, hipStream_t s);
 // Divide-and-conquer combination choice (best[c2] for every community C1 + c2).
 int union_combine_choice(const SparseBM &bm, int C1, int C2, int *best, hipStream_t s);
 // Sparse blockmodel of one graph for C labels, built in a single-graph workspace.

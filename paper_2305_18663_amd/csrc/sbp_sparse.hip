@@ -447,11 +447,13 @@ __device__ __forceinline__ void lists_lookup(const MoveLists &L, int nmax, int t
 
 // The four entries (M_rt, M_st, M_tr, M_ts) of a move from r to s for the
 // neighbour block t (union ids): one load each from the graph's lookup table
-// (C x C, when the step gave it one), else searches of the staged lists.
+// when use_tab (the graph has one and a row or column of r or s is longer
+// than the LDS stage), else searches of the staged lists (an LDS search beats
+// a table load when the lists fit the stage).
 template <int ROW>
-__device__ __forceinline__ void entries4(const GDev &d, const MoveLists &L, int nmax, int r, int s, int t,
-                                         int out[4]) {
-    if (d.mdense) {
+__device__ __forceinline__ void entries4(const GDev &d, bool use_tab, const MoveLists &L, int nmax, int r, int s,
+                                         int t, int out[4]) {
+    if (use_tab) {
         const int C = d.C, rl = r - d.boff, sl = s - d.boff, tl = t - d.boff;
         const int *__restrict__ M = d.mdense;
         out[0] = M[rl * C + tl];
@@ -586,7 +588,8 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
             ML.samp = SC[wv];
             ML.sampled = 0;
             ML.n[0] = ML.n[1] = ML.n[2] = ML.n[3] = 0;
-            if (!d.mdense) {  // with a lookup table no list is needed
+            const bool rlong = rb1 - rb0 > LEAF_ROW || cb1 - cb0 > LEAF_ROW;
+            if (!(d.mdense && rlong)) {  // long lists of a graph with a table are not staged
                 stage_list<LEAF_ROW>(ML, 0, bm.rcol + rb0, bm.rval + rb0, rb1 - rb0, SC[wv], SV[wv], lane, 64);
                 stage_list<LEAF_ROW>(ML, 2, bm.crow + cb0, bm.cval + cb0, cb1 - cb0, SC[wv], SV[wv], lane, 64);
             }
@@ -618,10 +621,14 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
                 continue;
             }
             // row s and column s of M
-            if (!d.mdense) {
+            bool use_tab;
+            {
                 const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
-                stage_list<LEAF_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
-                stage_list<LEAF_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
+                use_tab = d.mdense && (rlong || rs1 - rs0 > LEAF_ROW || cs1 - cs0 > LEAF_ROW);
+                if (!use_tab) {
+                    stage_list<LEAF_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[wv], SV[wv], lane, 64);
+                    stage_list<LEAF_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[wv], SV[wv], lane, 64);
+                }
             }
             const int dos = bm.dout[s], dis = bm.din[s];
             ell = wave_sum_i32(ell);
@@ -702,7 +709,7 @@ __global__ void __launch_bounds__(LEAF_WAVES * 64) __attribute__((amdgpu_waves_p
                 const int kp = ko | ki << 16;
                 const long long dtt = (long long)bm.dout[t] + bm.din[t];
                 int Mv[4];
-                entries4<LEAF_ROW>(d, ML, nmax, r, s, t, Mv);
+                entries4<LEAF_ROW>(d, use_tab, ML, nmax, r, s, t, Mv);
                 if (t == r) {
                     CV[wv][0] = Mv[0];  // M_rr
                     CV[wv][1] = Mv[1];  // M_sr
@@ -823,7 +830,8 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
             ML.samp = SC[gs];
             ML.sampled = 0;
             ML.n[0] = ML.n[1] = ML.n[2] = ML.n[3] = 0;
-            if (!d.mdense) {  // with a lookup table no list is needed
+            const bool rlong = b1r - b0r > SMALL_ROW || c1r - c0r > SMALL_ROW;
+            if (!(d.mdense && rlong)) {  // long lists of a graph with a table are not staged
                 stage_list<SMALL_ROW>(ML, 0, bm.rcol + b0r, bm.rval + b0r, b1r - b0r, SC[gs], SV[gs], gl, GS);
                 stage_list<SMALL_ROW>(ML, 2, bm.crow + c0r, bm.cval + c0r, c1r - c0r, SC[gs], SV[gs], gl, GS);
             }
@@ -885,10 +893,14 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 record_move(d, v, r, o, true, nb, tr);
             }
             // row s and column s of M
-            if (!d.mdense) {
+            bool use_tab;
+            {
                 const int rs0 = bm.rptr[s], rs1 = bm.rptr[s + 1], cs0 = bm.cptr[s], cs1 = bm.cptr[s + 1];
-                stage_list<SMALL_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[gs], SV[gs], gl, GS);
-                stage_list<SMALL_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[gs], SV[gs], gl, GS);
+                use_tab = d.mdense && (rlong || rs1 - rs0 > SMALL_ROW || cs1 - cs0 > SMALL_ROW);
+                if (!use_tab) {
+                    stage_list<SMALL_ROW>(ML, 1, bm.rcol + rs0, bm.rval + rs0, rs1 - rs0, SC[gs], SV[gs], gl, GS);
+                    stage_list<SMALL_ROW>(ML, 3, bm.crow + cs0, bm.cval + cs0, cs1 - cs0, SC[gs], SV[gs], gl, GS);
+                }
             }
             const int dos = bm.dout[s], dis = bm.din[s];
             ell = grp_sum_i32<GS>(ell);
@@ -932,7 +944,7 @@ __global__ void __launch_bounds__(SMALL_WAVES * 64) __attribute__((amdgpu_waves_
                 }
                 const long long dtt = (long long)bm.dout[tt] + bm.din[tt];
                 int Mv[4];
-                entries4<SMALL_ROW>(d, ML, nmax, r, s, tt, Mv);
+                entries4<SMALL_ROW>(d, use_tab, ML, nmax, r, s, tt, Mv);
                 if (tt == r) {
                     CV[gs][0] = Mv[0];  // M_rr
                     CV[gs][1] = Mv[1];  // M_sr
@@ -1732,36 +1744,213 @@ int union_sweep(const GDev *dG, const StepMeta &m, const SparseBM &bm, UnionScra
     return 0;
 }
 
-// Lookup tables of M (C x C ints, graph-local ids) for the listed graphs,
-// from the union rows: the graph's workgroups zero its table, then scatter
-// its rows (a second launch, so every zero lands first).
-__global__ void __launch_bounds__(BLK) k_table_zero(const GDev *__restrict__ G, const int *__restrict__ list,
-                                                    int n_list, int per) {
-    const GDev &d = G[list[blockIdx.x / per]];
-    const long long CC = (long long)d.C * d.C;
-    for (long long i = (long long)(blockIdx.x % per) * BLK + threadIdx.x; i < CC; i += (long long)per * BLK)
-        d.mdense[i] = 0;
+// The graph owning union block t (blocks of graph g are [boff, boff + C)).
+__device__ __forceinline__ int graph_of_block(const GDev *G, int nG, int t) {
+    int lo = 0, hi = nG - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G[mid].boff <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
-__global__ void __launch_bounds__(BLK) k_table_fill(const GDev *__restrict__ G, const int *__restrict__ list,
-                                                    int n_list, int per, SparseBM bm) {
-    const GDev &d = G[list[blockIdx.x / per]];
-    const int p0 = bm.rptr[d.boff], p1 = bm.rptr[d.boff + d.C];
-    for (int q = p0 + (blockIdx.x % per) * BLK + threadIdx.x; q < p1; q += per * BLK) {
-        // the row of entry q: last block whose rows start at or before q
-        int lo = d.boff, hi = d.boff + d.C - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (bm.rptr[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        d.mdense[(lo - d.boff) * d.C + (bm.rcol[q] - d.boff)] = bm.rval[q];
+
+// Lookup tables of M (C x C ints, graph-local ids) of the graphs that have
+// one: a wave per union block zeroes its table row, then (second launch, so
+// every zero lands first) a wave per union block writes its sparse row.
+// Blocks past a graph's (lowered) count have no row.
+__global__ void __launch_bounds__(BLK) k_table_zero_rows(const GDev *__restrict__ G, int nG, int Ctot) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int t = gw; t < Ctot; t += nw) {
+        const GDev &d = G[graph_of_block(G, nG, t)];
+        const int a = t - d.boff;
+        if (!d.mdense || a >= d.C) continue;
+        int *__restrict__ row = d.mdense + (size_t)a * d.C;
+        for (int x = lane; x < d.C; x += 64) row[x] = 0;
+    }
+}
+__global__ void __launch_bounds__(BLK) k_table_fill_rows(const GDev *__restrict__ G, int nG, int Ctot, SparseBM bm) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int t = gw; t < Ctot; t += nw) {
+        const GDev &d = G[graph_of_block(G, nG, t)];
+        const int a = t - d.boff;
+        if (!d.mdense || a >= d.C) continue;
+        int *__restrict__ row = d.mdense + (size_t)a * d.C;
+        for (int q = bm.rptr[t] + lane; q < bm.rptr[t + 1]; q += 64) row[bm.rcol[q] - d.boff] = bm.rval[q];
     }
 }
 
-int union_lookup_tables(const GDev *dG, const int *list, int n_list, const SparseBM &bm, hipStream_t s) {
+// ---------------------------------------------------------------- build from tables
+// When every graph of a step has a C x C table (C <= SBP_TABLE_MAX_C), M is
+// counted straight into the tables (one integer atomic per edge), and the
+// sorted rows, sorted columns, proposal rows with running sums and block
+// degrees are read off the tables in ascending order: the same arrays as the
+// sort-based build, at O(sum C^2) instead of several radix passes over the
+// edges.
+
+// M of every graph into its table (zeroed beforehand); edges in flattened
+// per-block ranges as in k_edge_keys.
+__global__ void __launch_bounds__(BLK) k_tab_hist(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG,
+                                                  int Ntot) {
+    __shared__ long long U[BLK + 1];
+    __shared__ int gi[BLK], ra[BLK];
+    for (int b0 = blockIdx.x * BLK; b0 < Ntot; b0 += gridDim.x * BLK) {
+        const int nv = min(BLK, Ntot - b0);
+        __syncthreads();
+        if ((int)threadIdx.x < nv) {
+            const int t = threadIdx.x, i = b0 + t;
+            const int g = find_graph(vstart, nG, i);
+            const GDev &d = G[g];
+            const int v = i - d.voff;
+            U[t] = d.eoff + d.out_ptr[v];
+            ra[t] = d.lab[v] * d.C;
+            gi[t] = g;
+            if (t == nv - 1) U[nv] = d.eoff + d.out_ptr[v + 1];
+        }
+        __syncthreads();
+        const long long e1 = U[nv];
+        for (long long x = U[0] + threadIdx.x; x < e1; x += BLK) {
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (U[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            const GDev &d = G[gi[lo]];
+            atomicAdd(&d.mdense[ra[lo] + d.lab[d.out_idx[x - d.eoff]]], 1);
+        }
+    }
+}
+
+// Per union block: nonzeros of its row and of its column, and the degrees.
+__global__ void __launch_bounds__(BLK) k_tab_counts(const GDev *__restrict__ G, int nG, int Ctot, SparseBM bm,
+                                                    int *__restrict__ rlen, int *__restrict__ clen) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int t = gw; t < Ctot; t += nw) {
+        const GDev &d = G[graph_of_block(G, nG, t)];
+        const int a = t - d.boff;
+        const int C = a < d.C ? d.C : 0;  // a block past the graph's (lowered) count is empty
+        const int *__restrict__ T = d.mdense;
+        int nr = 0, nc = 0, so = 0, si = 0;
+        for (int x = lane; x < C; x += 64) {
+            const int r = T[a * C + x], c = T[x * C + a];
+            nr += r != 0;
+            nc += c != 0;
+            so += r;
+            si += c;
+        }
+        nr = wave_sum_i32(nr);
+        nc = wave_sum_i32(nc);
+        so = wave_sum_i32(so);
+        si = wave_sum_i32(si);
+        if (lane == 0) {
+            rlen[t] = nr;
+            clen[t] = nc;
+            bm.dout[t] = so;
+            bm.din[t] = si;
+        }
+    }
+}
+
+__global__ void k_tab_ptrs(const long long *__restrict__ pr, const long long *__restrict__ pc,
+                           const long long *__restrict__ tot, int Ctot, int *__restrict__ rptr, int *__restrict__ cptr,
+                           long long *__restrict__ nnz) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= Ctot; t += gridDim.x * blockDim.x) {
+        rptr[t] = t < Ctot ? (int)pr[t] : (int)tot[0];
+        cptr[t] = t < Ctot ? (int)pc[t] : (int)tot[1];
+        if (t == 0) *nnz = tot[0];
+    }
+}
+
+// Rows, columns and proposal rows of every union block, in ascending order:
+// a wave per block walks its table row and column 64 entries at a time and
+// places the nonzeros by ballot.  The proposal row takes, per column s, the
+// row entry (M_ts) then the column entry (M_st), with inclusive running sums.
+__global__ void __launch_bounds__(BLK) k_tab_emit(const GDev *__restrict__ G, int nG, int Ctot, SparseBM bm) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lanemask_lt();
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (int t = gw; t < Ctot; t += nw) {
+        const GDev &d = G[graph_of_block(G, nG, t)];
+        const int a = t - d.boff, b = d.boff;
+        const int C = a < d.C ? d.C : 0;  // a block past the graph's (lowered) count is empty
+        const int *__restrict__ T = d.mdense;
+        int pr = bm.rptr[t], pc = bm.cptr[t], ps = bm.rptr[t] + bm.cptr[t];
+        int carry = 0;
+        for (int x0 = 0; x0 < C; x0 += 64) {
+            const int x = x0 + lane;
+            const int r = x < C ? T[a * C + x] : 0, c = x < C ? T[x * C + a] : 0;
+            const uint64_t mr = __ballot(r != 0), mc = __ballot(c != 0);
+            if (r) {
+                const int k = pr + __popcll(mr & below);
+                bm.rcol[k] = b + x;
+                bm.rval[k] = r;
+            }
+            if (c) {
+                const int k = pc + __popcll(mc & below);
+                bm.crow[k] = b + x;
+                bm.cval[k] = c;
+            }
+            // proposal row: lane x holds up to two entries, row entry first
+            const int n_here = (r != 0) + (c != 0);
+            int off = n_here, v = r + c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {  // inclusive scans of entry counts and values
+                const int y = __shfl_up(off, o, SBP_WAVE), z = __shfl_up(v, o, SBP_WAVE);
+                if (lane >= o) {
+                    off += y;
+                    v += z;
+                }
+            }
+            const int k0 = ps + off - n_here;  // the lane's first slot
+            const int base = carry + v - (r + c);
+            if (r) {
+                bm.scol[k0] = b + x;
+                bm.scum[k0] = base + r;
+            }
+            if (c) {
+                bm.scol[k0 + (r != 0)] = b + x;
+                bm.scum[k0 + (r != 0)] = base + r + c;
+            }
+            pr += __popcll(mr);
+            pc += __popcll(mc);
+            ps += __shfl(off, 63, SBP_WAVE);
+            carry += __shfl(v, 63, SBP_WAVE);
+        }
+    }
+}
+
+int build_union_from_tables(const GDev *dG, const StepMeta &m, SparseBM &bm, UnionScratch &ws,
+                            const int *list, int n_list, hipStream_t s) {
+    const int Ctot = m.Ctot;
+    bm.Ctot = Ctot;
+    (void)list;
+    (void)n_list;
+    hipLaunchKernelGGL(k_table_zero_rows, dim3(grid_for((long long)Ctot * 64, BLK, 8192)), dim3(BLK), 0, s, dG, m.G,
+                       Ctot);
+    hipLaunchKernelGGL(k_tab_hist, dim3(grid_for(m.Ntot, BLK, 16384)), dim3(BLK), 0, s, dG, m.voff, m.G,
+                       (int)m.Ntot);
+    int *rlen = ws.i0, *clen = ws.i1;
+    hipLaunchKernelGGL(k_tab_counts, dim3(grid_for((long long)Ctot * 64, BLK, 8192)), dim3(BLK), 0, s, dG, m.G, Ctot,
+                       bm, rlen, clen);
+    SBP_LAUNCH_CHECK();
+    int rc;
+    long long *tot = (long long *)ws.v1;  // two totals (the sort buffers are not used on this path)
+    if ((rc = scan_exclusive_i32(rlen, ws.s0, Ctot, tot + 0, ws.temp, s))) return rc;
+    if ((rc = scan_exclusive_i32(clen, ws.s1, Ctot, tot + 1, ws.temp, s))) return rc;
+    hipLaunchKernelGGL(k_tab_ptrs, dim3(grid_for(Ctot + 1, BLK, 4096)), dim3(BLK), 0, s, (const long long *)ws.s0,
+                       (const long long *)ws.s1, (const long long *)tot, Ctot, bm.rptr, bm.cptr, bm.nnz);
+    hipLaunchKernelGGL(k_tab_emit, dim3(grid_for((long long)Ctot * 64, BLK, 8192)), dim3(BLK), 0, s, dG, m.G, Ctot, bm);
+    SBP_LAUNCH_CHECK();
+    return 0;
+}
+
+int union_lookup_tables(const GDev *dG, int nG, int n_list, const SparseBM &bm, hipStream_t s) {
     if (n_list <= 0) return 0;
-    constexpr int PER = 16;  // workgroups per graph
-    hipLaunchKernelGGL(k_table_zero, dim3(n_list * PER), dim3(BLK), 0, s, dG, list, n_list, PER);
-    hipLaunchKernelGGL(k_table_fill, dim3(n_list * PER), dim3(BLK), 0, s, dG, list, n_list, PER, bm);
+    const int grid = grid_for((long long)bm.Ctot * 64, BLK, 8192);
+    hipLaunchKernelGGL(k_table_zero_rows, dim3(grid), dim3(BLK), 0, s, dG, nG, bm.Ctot);
+    hipLaunchKernelGGL(k_table_fill_rows, dim3(grid), dim3(BLK), 0, s, dG, nG, bm.Ctot, bm);
     SBP_LAUNCH_CHECK();
     return 0;
 }

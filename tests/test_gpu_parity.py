@@ -665,13 +665,19 @@ def test_lookup_tables_change_nothing():
     dgs = [sbp.DeviceGraph(x) for x in graphs]
     kw = [dict(seed=90 + i) for i in range(len(graphs))]
     try:
-        a = sbp.sbp_partition_batch(dgs, kw)
+        sbp.sbp_tune("table_build", 2)
+        a = sbp.sbp_partition_batch(dgs, kw)  # M counted into the tables whenever every count fits
+        sbp.sbp_tune("table_build", 0)
+        b = sbp.sbp_partition_batch(dgs, kw)  # tables as lookups only, the sort-based build
         sbp.sbp_tune("table_max_c", 0)
-        b = sbp.sbp_partition_batch(dgs, kw)
+        c = sbp.sbp_partition_batch(dgs, kw)  # no tables
     finally:
         sbp.sbp_tune("table_max_c", 2048)
-    for x, y in zip(a, b):
-        assert x["C"] == y["C"] and x["dl"] == y["dl"] and np.array_equal(x["lab"], y["lab"])
+        sbp.sbp_tune("table_build", 1)
+    for x, y, z in zip(a, b, c):
+        assert x["C"] == y["C"] == z["C"] and x["dl"] == y["dl"] == z["dl"]
+        assert np.array_equal(x["lab"], y["lab"]) and np.array_equal(x["lab"], z["lab"])
+        assert np.array_equal(x["trace_dl"], z["trace_dl"])
 
 
 def test_batch_matches_oracle():
