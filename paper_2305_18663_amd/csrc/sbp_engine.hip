@@ -327,6 +327,7 @@ struct UnionLayout {
 constexpr size_t DSLOT_BYTES = 64 * 64 * 4 + 64 * 64 * 8 + 2 * 64 * 4;
 int g_engine_dense_max_c = SBP_DENSE_MAX_C;  // engine sweeps at C <= this use the dense kernels (0: never)
 int g_table_max_c = SBP_TABLE_MAX_C;         // sparse sweeps at C <= this read M from a lookup table (0: never)
+int g_table_ratio = 4;  // automatic table builds need ratio * cost <= 16 * edges (4: cost <= 4 E)
 int g_table_build = 1;  // count M into the tables: 0 never, 1 when they are small against the edges, 2 whenever all fit
 
 UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
@@ -980,15 +981,23 @@ int engine_step(sbp_engine *eng, int *active_out) {
         // worth it when the tables are small against the edges: the build
         // then scans sum C^2 entries (columns with a stride of C) instead of
         // radix-sorting every edge's key several times
-        long long need = 0, sq = 0, edges = 0;
+        // (graphs above 64 blocks count with global atomics: at most 64 edges
+        // per cell on average, or the atomics serialise)
+        // cost model: a table scan against the sort of every edge key; columns
+        // are read with a stride of C, which costs about four times more once
+        // a table row no longer fits a few cache lines
+        long long need = 0, cost = 0, edges = 0;
+        bool spread = true;
         for (int g = 0; g < G && all_tabled; ++g) {
-            const long long Cb = eng->active[g]->C;
+            const long long Cb = eng->active[g]->C, e = eng->active[g]->g.e;
             all_tabled = Cb <= g_table_max_c;
             need += (Cb * Cb + 63) & ~63LL;
-            sq += Cb * Cb;
-            edges += eng->active[g]->g.e;
+            cost += Cb * Cb * (Cb > 512 ? 4 : 1);
+            edges += e;
+            spread = spread && (Cb <= SBP_DENSE_MAX_C || e <= 64 * Cb * Cb);
         }
-        all_tabled = all_tabled && need <= u.table_ints && (g_table_build == 2 || 8 * sq <= edges);
+        const bool cheap = spread && cost * g_table_ratio <= 16 * edges;
+        all_tabled = all_tabled && need <= u.table_ints && (g_table_build == 2 || cheap);
     }
     for (int g = 0; g < G; ++g) {
         hG[g] = desc_of(*eng->active[g]);
@@ -1746,6 +1755,10 @@ int sbp_tune(const char *key, int64_t value) {
     }
     if (!strcmp(key, "table_max_c") && value >= 0 && value <= SBP_TABLE_MAX_C) {
         g_table_max_c = (int)value;
+        return 0;
+    }
+    if (!strcmp(key, "table_build_ratio") && value >= 1 && value <= 1024) {
+        g_table_ratio = (int)value;
         return 0;
     }
     if (!strcmp(key, "table_build") && value >= 0 && value <= 2) {

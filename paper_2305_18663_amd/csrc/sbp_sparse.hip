@@ -1793,8 +1793,10 @@ __global__ void __launch_bounds__(BLK) k_table_fill_rows(const GDev *__restrict_
 // per-block ranges as in k_edge_keys.
 __global__ void __launch_bounds__(BLK) k_tab_hist(const GDev *__restrict__ G, const int *__restrict__ vstart, int nG,
                                                   int Ntot) {
+    constexpr int HCELLS = SBP_DENSE_MAX_C_DEV * SBP_DENSE_MAX_C_DEV;
     __shared__ long long U[BLK + 1];
     __shared__ int gi[BLK], ra[BLK];
+    __shared__ int H[HCELLS];  // a workgroup's own counts when its range lies in one graph with C <= 64
     for (int b0 = blockIdx.x * BLK; b0 < Ntot; b0 += gridDim.x * BLK) {
         const int nv = min(BLK, Ntot - b0);
         __syncthreads();
@@ -1809,6 +1811,13 @@ __global__ void __launch_bounds__(BLK) k_tab_hist(const GDev *__restrict__ G, co
             if (t == nv - 1) U[nv] = d.eoff + d.out_ptr[v + 1];
         }
         __syncthreads();
+        // one graph with few blocks: count in LDS first (many edges share a
+        // handful of cells, which global atomics would serialise)
+        const GDev &d0 = G[gi[0]];
+        const bool local = gi[0] == gi[nv - 1] && d0.C <= SBP_DENSE_MAX_C_DEV;
+        const int CC = local ? d0.C * d0.C : 0;
+        for (int c = threadIdx.x; c < CC; c += BLK) H[c] = 0;
+        __syncthreads();
         const long long e1 = U[nv];
         for (long long x = U[0] + threadIdx.x; x < e1; x += BLK) {
             int lo = 0, hi = nv - 1;
@@ -1817,8 +1826,13 @@ __global__ void __launch_bounds__(BLK) k_tab_hist(const GDev *__restrict__ G, co
                 if (U[mid] <= x) lo = mid; else hi = mid - 1;
             }
             const GDev &d = G[gi[lo]];
-            atomicAdd(&d.mdense[ra[lo] + d.lab[d.out_idx[x - d.eoff]]], 1);
+            const int cell = ra[lo] + d.lab[d.out_idx[x - d.eoff]];
+            if (local) atomicAdd(&H[cell], 1);
+            else atomicAdd(&d.mdense[cell], 1);
         }
+        __syncthreads();
+        for (int c = threadIdx.x; c < CC; c += BLK)
+            if (H[c]) atomicAdd(&d0.mdense[c], H[c]);
     }
 }
 
