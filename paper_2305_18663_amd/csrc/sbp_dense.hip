@@ -301,22 +301,23 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
     }
 }
 
-// Inclusive prefix sum over the 8 lanes of a scoring group (gl = lane in the
-// group): row shifts, with the lanes whose source lies in the group before
-// left out.
-__device__ __forceinline__ int grp8_scan(int x, int gl) {
+// Inclusive prefix sum over the GS = 4 or 8 lanes of a scoring group (gl =
+// lane in the group): row shifts, with the lanes whose source lies in the
+// group before left out.
+template <int GS>
+__device__ __forceinline__ int grp_scan(int x, int gl) {
     int y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
     if (gl >= 1) x += y;
     y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
     if (gl >= 2) x += y;
-    y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-    if (gl >= 4) x += y;
+    if (GS >= 8) {
+        y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+        if (gl >= 4) x += y;
+    }
     return x;
 }
 
 constexpr int EVAL_T = 256;      // threads per workgroup
-constexpr int GS = 8;            // lanes per vertex in the scoring phase (half a DPP row)
-constexpr int NG = EVAL_T / GS;  // scoring groups per workgroup
 constexpr int SEG = 8;           // consecutive edge ends per thread in the histogram phase
 constexpr int LDS_CU = 160 * 1024;
 
@@ -345,19 +346,25 @@ struct EvalArgs {
 // rows are CM apart.
 template <int CM>
 struct EvalLds {
-    static constexpr int CH = CM >= 48 ? 32 : 64;  // vertices per chunk: four workgroups per CU up to 48 blocks
+    // lanes per vertex in the scoring phase: four up to 48 blocks (sixteen
+    // vertices per wave), eight (half a DPP row) beyond
+    static constexpr int GS = CM > 48 ? 8 : 4;
+    static constexpr int NG = EVAL_T / GS;         // scoring groups per workgroup
+    static constexpr int CH = CM > 48 ? 32 : 64;  // vertices per chunk
+    // waves a SIMD can hold with this LDS (three workgroups a CU up to 48
+    // blocks, two beyond): the register budget follows from it
+    static constexpr int WAVES = CM > 48 ? 2 : 3;
     static constexpr int RS = CM + 1;
     double fM[CM * RS];
     double fdo[CM], fdi[CM], inv[CM];
-    uint64_t W[3][CH];  // Philox words 1-3 of the chunk's vertices
+    uint64_t W[4][CH];  // Philox words 0-3 of the chunk's vertices
     long long wst[3 * (EVAL_T / 64)];
     double wsd[EVAL_T / 64];
     int Ms[CM * RS];
     int dsum[CM], dos[CM], dis[CM];
     unsigned H[CH * CM];  // out-ends in the low 16 bits, in-ends in the high 16 bits
     int v[CH], r[CH], op[CH + 1], kout[CH], ip[CH + 1], kin[CH], pre[CH + 1], ell[CH], t0[CH], j0[CH];
-    unsigned char items[NG][CM];
-    int ord[CH];  // scoring order: by degree, larger first
+    unsigned char items[NG][CM + 1];  // the last byte takes the writes of unlisted blocks
 };
 template <int CM>
 constexpr int eval_chunk() { return EvalLds<CM>::CH; }
@@ -368,21 +375,24 @@ constexpr int eval_wgs_per_cu() {
 
 // Sweep batch evaluation against the snapshot M.  A workgroup takes CH batch
 // vertices at a time:
-//  (0) their pointers, labels and Philox words (wave 0);
+//  (0) their pointers, labels and end prefix (wave 0), their Philox words and
+//      end draws (wave 1) and empty histogram rows (waves 2-3), together;
 //  (A) every edge end of the chunk into packed per-vertex block histograms in
 //      LDS: a thread takes SEG consecutive ends of the chunk's flattened end
 //      list, finds their owners with one search and a forward walk, issues all
 //      its loads, then counts.  With ENDS the far-end blocks are the stored end
 //      bytes; otherwise (one batch of several) the ids are read and the labels
 //      gathered;
-//  (B) a group of GS lanes scores one vertex per round: the
-//      proposal from running sums of e_t0. built on the fly from M (exact
-//      integer row scans), the vertex's nonzero blocks t != r, s compacted into
-//      a list, then for every listed block the four changed entries of M --
-//      f of the old values from LDS, f of the new values gathered from the
-//      table, a batch of gathers (with the 2x2 corner and the block degrees) in
-//      flight together -- the Hastings terms, group sums on DPP and
-//      the three logs of the wave's eight vertices in one evaluation.
+//  (B) a group of GS lanes (four, or eight past 48 blocks) scores one vertex
+//      per round: the proposal from running sums of e_t0. built on the fly
+//      from M (exact integer sums, lane gl owning NQ consecutive blocks, one
+//      group scan), the vertex's nonzero blocks t != r, s compacted into a
+//      list in block order, then for every listed block the four changed
+//      entries of M -- f of the old values from LDS, f of the new values
+//      gathered from the table, a batch of gathers (with the 2x2 corner and
+//      the block degrees) in flight together -- the Hastings terms, group
+//      sums on DPP and the three logs of the wave's 64 / GS vertices in one
+//      evaluation.
 // The decision goes to nb: with ENDS one byte per vertex (0xff = stays),
 // otherwise an int (-1 = stays).  TRACE adds the per-vertex record.
 //
@@ -428,6 +438,8 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
     using Lds = EvalLds<CM>;
     constexpr int CH = Lds::CH;
     constexpr int RS = Lds::RS;
+    constexpr int GS = Lds::GS, NG = Lds::NG;
+    constexpr unsigned GMASK = (1u << GS) - 1u;
     constexpr int NQ = CM / GS;  // blocks per lane in the scoring phase
     constexpr int BQ = NQ < 2 ? NQ : 2;  // slots per batch of table gathers
     static_assert(CH % NG == 0, "every group scores the same number of vertices per chunk");
@@ -462,53 +474,55 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
         const int base = chunk * CH;
         const int nv = min(CH, nbc - base);
         __syncthreads();  // previous chunk done with the LDS
-        // (0) vertex data and words
-        if (tid < 64) {
+        // (0) three waves in parallel: the chunk's vertex data (wave 0), the
+        // Philox words (wave 1), empty histograms (the rest)
+        if (wv == 0) {
             int k = 0;
-            if (tid < nv) {
-                const int v = a.batch + (base + tid) * a.n_batches;
+            if (lane < nv) {
+                const int v = a.batch + (base + lane) * a.n_batches;
                 const int op = a.out_ptr[v], ko = a.out_ptr[v + 1] - op;
                 const int ip = a.in_ptr[v], ki = a.in_ptr[v + 1] - ip;
-                L.v[tid] = v;
-                L.r[tid] = a.lab[v];
-                L.op[tid] = op;
-                L.kout[tid] = ko;
-                L.ip[tid] = ip;
-                L.kin[tid] = ki;
+                L.v[lane] = v;
+                L.r[lane] = a.lab[v];
+                L.op[lane] = op;
+                L.kout[lane] = ko;
+                L.ip[lane] = ip;
+                L.kin[lane] = ki;
+                L.ell[lane] = 0;
                 k = ko + ki;
-                uint32_t wa[4], wb[4];
-                philox_block((uint32_t)v, sweep, 0u, 0u, k0, k1, wa);
-                philox_block((uint32_t)v, sweep, 1u, 0u, k0, k1, wb);
-                const uint64_t W0 = (uint64_t)wa[0] | ((uint64_t)wa[1] << 32);
-                L.W[0][tid] = (uint64_t)wa[2] | ((uint64_t)wa[3] << 32);
-                L.W[1][tid] = (uint64_t)wb[0] | ((uint64_t)wb[1] << 32);
-                L.W[2][tid] = (uint64_t)wb[2] | ((uint64_t)wb[3] << 32);
-                L.j0[tid] = k > 0 ? (int)draw_idx(W0, (uint64_t)k) : -1;
-                L.ell[tid] = 0;
-                if (tid == nv - 1) {  // ends of the chunk's ranges (consecutive vertices)
+                if (lane == nv - 1) {  // ends of the chunk's ranges (consecutive vertices)
                     L.op[nv] = op + ko;
                     L.ip[nv] = ip + ki;
                 }
             }
-            // exclusive prefix of the edge-end counts (wave 0)
+            // exclusive prefix of the edge-end counts
             int x = k;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int y = __shfl_up(x, o, SBP_WAVE);
                 if (lane >= o) x += y;
             }
-            if (tid < CH) L.pre[tid + 1] = x;
-            if (tid == 0) L.pre[0] = 0;
-            // scoring order: by degree, larger first, ties by position
-            const int key = tid < nv ? k : -1;
-            int rank = 0;
-            for (int j = 0; j < CH; ++j) {
-                const int kj = __builtin_amdgcn_readlane(key, j);
-                rank += (kj > key || (kj == key && j < tid)) ? 1 : 0;
+            if (lane < CH) L.pre[lane + 1] = x;
+            if (lane == 0) L.pre[0] = 0;
+        } else if (wv == 1) {
+            // blocks (v, sweep, 0, 0) and (v, sweep, 1, 0): words W0, W1 and W2, W3
+            for (int i = lane; i < 2 * CH; i += 64) {
+                const int vi = i % CH, blk = i / CH;
+                if (vi < nv) {
+                    const int v = a.batch + (base + vi) * a.n_batches;
+                    // the degree for the end draw j0 (the same words wave 0 reads)
+                    const int k = blk ? 0 : a.out_ptr[v + 1] - a.out_ptr[v] + a.in_ptr[v + 1] - a.in_ptr[v];
+                    uint32_t o[4];
+                    philox_block((uint32_t)v, sweep, (uint32_t)blk, 0u, k0, k1, o);
+                    const uint64_t Wa = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+                    L.W[2 * blk][vi] = Wa;
+                    L.W[2 * blk + 1][vi] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+                    if (!blk) L.j0[vi] = k > 0 ? (int)draw_idx(Wa, (uint64_t)k) : -1;
+                }
             }
-            if (tid < CH) L.ord[rank] = tid;
+        } else {
+            for (int i = tid - 128; i < CH * CM; i += EVAL_T - 128) L.H[i] = 0;
         }
-        for (int i = tid; i < CH * CM; i += EVAL_T) L.H[i] = 0;
         __syncthreads();
         if constexpr (ENDS) {
             // (A) histograms from the end bytes: the chunk's vertices are
@@ -620,83 +634,109 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
             }
         }
         __syncthreads();
-        // (B) scoring, one vertex per group per round, in degree order (so the
-        // eight vertices of a wave need about as many slots); every group runs
-        // the same number of rounds, so DPP and ballots see whole groups
-        const unsigned below = (1u << gl) - 1u;
-        for (int slot = grp; slot < CH; slot += NG) {
-            const int vi = L.ord[slot];
+        // (B) scoring, one vertex per group per round; every group runs the
+        // same number of rounds, so DPP and ballots see whole groups.  The
+        // round is written without branches: every LDS read is issued whatever
+        // the conditions (all indices stay inside the arrays) and the
+        // conditions select among the values, so the reads of a step are in
+        // flight together instead of one waited-for read per condition.
+        for (int vi = grp; vi < CH; vi += NG) {
             const bool valid = vi < nv;
-            int v = 0, r = 0, kout = 0, kin = 0, ell = 0, t0 = 0;
-            uint64_t W1 = 0, W2 = 0, W3 = 0;
-            if (valid) {
-                v = L.v[vi];
-                r = L.r[vi];
-                kout = L.kout[vi];
-                kin = L.kin[vi];
-                ell = L.ell[vi];
-                t0 = kout + kin > 0 ? L.t0[vi] : 0;
-                W1 = L.W[0][vi];
-                W2 = L.W[1][vi];
-                W3 = L.W[2][vi];
-            }
+            const int v_ = L.v[vi], r_ = L.r[vi], ko_ = L.kout[vi], ki_ = L.kin[vi];
+            const int ell_ = L.ell[vi], t0_ = L.t0[vi];
+            const uint64_t W1 = L.W[1][vi], W2 = L.W[2][vi], W3 = L.W[3][vi];
+            const int v = valid ? v_ : 0, r = valid ? r_ : 0;
+            const int kout = valid ? ko_ : 0, kin = valid ? ki_ : 0, ell = valid ? ell_ : 0;
             const int k = kout + kin;
+            const int t0 = k > 0 ? t0_ : 0;
             const unsigned *Hv = L.H + vi * CM;
             // proposal: a uniform block, or the first block b whose running
-            // sum of e_t0,b' = M_t0,b' + M_b',t0 over b' <= b exceeds x
+            // sum of e_t0,b' = M_t0,b' + M_b',t0 over b' <= b exceeds x; lane
+            // gl holds the blocks gl NQ .. gl NQ + NQ - 1
+            const int b0 = gl * NQ;
             int s;
             {
-                const long long dt = k > 0 ? (long long)L.dsum[t0] : 0;
-                const bool unif = k == 0 || draw_idx(W1, (uint64_t)(dt + eC)) < (uint64_t)eC;
+                const int dt0 = L.dsum[t0];
+                const long long dt = k > 0 ? (long long)dt0 : 0;
+                const bool unif = (k == 0) | (draw_idx(W1, (uint64_t)(dt + eC)) < (uint64_t)eC);
                 const long long x = unif ? 0 : (long long)draw_idx(W2, (uint64_t)dt);
-                int sp = C;
-                long long carry = 0;
+                int ev[NQ], lsum = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const int bb = q * GS + gl;
-                    const int e0 = L.Ms[t0 * RS + bb] + L.Ms[bb * RS + t0];  // within the padded rows
-                    const int e = (!unif && bb < C) ? e0 : 0;
-                    const int run = grp8_scan(e, gl);
-                    const bool hit = !unif && bb < C && carry + run > x;
-                    const unsigned m = (unsigned)(__ballot(hit) >> (wgrp * GS)) & 0xffu;
-                    sp = (m && sp == C) ? q * GS + __builtin_ctz(m) : sp;
-                    carry += __shfl(run, wgrp * GS + GS - 1, SBP_WAVE);
+                    const int e0 = L.Ms[t0 * RS + b0 + q] + L.Ms[(b0 + q) * RS + t0];  // padded rows
+                    ev[q] = (!unif & (b0 + q < C)) ? e0 : 0;
+                    lsum += ev[q];
                 }
-                s = unif ? (int)draw_idx(W2, (uint64_t)C) : sp;
-            }
-            const bool hub = valid && a.hubrank && a.hubrank[v] > 0;  // moved one at a time before this pass
-            const bool act = valid && !hub && s != r;
-            if (!act) s = r;  // keeps every index below in range
-            // blocks t != r, s with a neighbour: a compacted list
-            unsigned char *items = L.items[grp];
-            int n_it = 0;
+                const int incl = grp_scan<GS>(lsum, gl);
+                const unsigned m = (unsigned)(__ballot(!unif & ((long long)incl > x)) >> (wgrp * GS)) & GMASK;
+                long long acc = (long long)(incl - lsum);
+                int cand = C;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int t = q * GS + gl;
-                const unsigned hv = Hv[t];  // within the padded row
-                const bool nz = act && t < C && t != r && t != s && hv != 0u;
-                const unsigned m = (unsigned)(__ballot(nz) >> (wgrp * GS)) & 0xffu;
-                if (nz) items[n_it + __builtin_popcount(m & below)] = (unsigned char)t;
-                n_it += __builtin_popcount(m);
+                for (int q = 0; q < NQ; ++q) {
+                    acc += ev[q];
+                    cand = ((cand == C) & (acc > x)) ? b0 + q : cand;
+                }
+                const int sp = __shfl(cand, wgrp * GS + (m ? __builtin_ctz(m) : 0), SBP_WAVE);
+                s = unif ? (int)draw_idx(W2, (uint64_t)C) : (m ? sp : C);
+            }
+            bool hub = false;  // moved one at a time before this pass
+            if (a.hubrank) {
+                const int hk = a.hubrank[v];
+                hub = valid & (hk > 0);
+            }
+            const bool act = valid & !hub & (s != r);
+            if (!act) s = r;  // keeps every index below in range
+            // blocks t != r, s with a neighbour: a compacted list in block
+            // order (lane gl writes its blocks after those of lanes < gl; a
+            // block that is not listed is written to the spare last byte)
+            unsigned char *items = L.items[grp];
+            int n_it;
+            {
+                unsigned nzm = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int t = b0 + q;
+                    const unsigned hv = Hv[t];  // within the padded row
+                    nzm |= (act & (t < C) & (t != r) & (t != s) & (hv != 0u)) ? 1u << q : 0u;
+                }
+                const int cnt = __builtin_popcount(nzm);
+                const int incl = grp_scan<GS>(cnt, gl);
+                n_it = __shfl(incl, wgrp * GS + GS - 1, SBP_WAVE);
+                int pos = incl - cnt;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const bool nz = (nzm >> q) & 1u;
+                    items[nz ? pos : CM] = (unsigned char)(b0 + q);
+                    pos += nz ? 1 : 0;
+                }
             }
             // the corner item of this lane: entries (lanes 0-3), degrees (4-7)
-            const unsigned hr = Hv[r], hs = Hv[s];
-            const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
-            const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
             const int c = gl & 3;
             const int ca = c < 2 ? r : s, cb = (c & 1) ? s : r;  // entry (ca, cb) of the corner
+            const int bc = (c & 1) ? s : r;                        // block of the degree term
+            const unsigned hr = Hv[r], hs = Hv[s];
+            const int m_c = L.Ms[ca * RS + cb], do_c = L.dos[bc], di_c = L.dis[bc];
+            const double fm_c = L.fM[ca * RS + cb], fdo_c = L.fdo[bc], fdi_c = L.fdi[bc];
+            const int Mrr = L.Ms[r * RS + r], Mrs = L.Ms[r * RS + s], Msr = L.Ms[s * RS + r], Mss = L.Ms[s * RS + s];
+            const int dsr_ = L.dsum[r], dss_ = L.dsum[s];
+            wave_sync_lds();  // the group's list is written
+            const int ko_r = (int)(hr & 0xffffu), ki_r = (int)(hr >> 16);
+            const int ko_s = (int)(hs & 0xffffu), ki_s = (int)(hs >> 16);
             const int mdelta = c == 0 ? -ko_r - ki_r - ell : c == 1 ? -ko_s + ki_r : c == 2 ? ko_r - ki_s : ko_s + ki_s + ell;
-            const bool is_m = gl < 4;
-            const int cdeg = c == 0 ? L.dos[r] : c == 1 ? L.dos[s] : c == 2 ? L.dis[r] : L.dis[s];
+            // the entry (lanes 0-3) or the degree term (lanes 4-7) of corner
+            // item c; with four lanes a group, both
+            const bool is_m = GS == 4 || gl < 4;
+            const int cdeg = c < 2 ? do_c : di_c;
             const int ddelta = c == 0 ? -kout : c == 1 ? kout : c == 2 ? -kin : kin;
-            const int c_new = is_m ? L.Ms[ca * RS + cb] + mdelta : cdeg + ddelta;
+            const int c_new = is_m ? m_c + mdelta : cdeg + ddelta;
             const double c_fnew = fx(tab, fmax, act ? c_new : 0);
+            const double d_fnew = GS == 4 ? fx(tab, fmax, act ? cdeg + ddelta : 0) : 0.0;
             double dL = 0.0, qf = 0.0, qr = 0.0;
             // listed blocks: four changed entries each, BQ slots per batch, a
             // batch only when a group of the wave needs it.  Within a batch no
             // branches: a slot without a block, or a count of zero, loads f(0)
             // (one line for the whole wave) and contributes an exact zero.
-#pragma unroll
+#pragma unroll 1
             for (int q0 = 0; q0 < NQ; q0 += BQ) {
                 if (!__any(q0 * GS < n_it)) break;
                 int ti[BQ];
@@ -706,7 +746,11 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
                     const int i = (q0 + q) * GS + gl;
                     const int t = items[i];
                     ti[q] = i < n_it ? t : 0;
-                    hq[q] = i < n_it ? Hv[ti[q]] : 0u;
+                }
+#pragma unroll
+                for (int q = 0; q < BQ; ++q) {
+                    const unsigned h = Hv[ti[q]];
+                    hq[q] = (q0 + q) * GS + gl < n_it ? h : 0u;
                 }
                 double fn[BQ][4];
 #pragma unroll
@@ -728,31 +772,37 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
                 for (int q = 0; q < BQ; ++q) {
                     const int t = ti[q];
                     const int ko = (int)(hq[q] & 0xffffu), ki = (int)(hq[q] >> 16);
-                    const double d_out = (fn[q][0] - L.fM[r * RS + t]) + (fn[q][1] - L.fM[s * RS + t]);
-                    const double d_in = (fn[q][2] - L.fM[t * RS + r]) + (fn[q][3] - L.fM[t * RS + s]);
+                    const double f0 = L.fM[r * RS + t], f1 = L.fM[s * RS + t];
+                    const double f2 = L.fM[t * RS + r], f3 = L.fM[t * RS + s];
+                    const double d_out = (fn[q][0] - f0) + (fn[q][1] - f1);
+                    const double d_in = (fn[q][2] - f2) + (fn[q][3] - f3);
                     dL += (ko ? d_out : 0.0) + (ki ? d_in : 0.0);
                 }
             }
-            if (act) {
-                const double c_fold = is_m ? L.fM[ca * RS + cb] : (c < 2 ? L.fdo[c == 0 ? r : s] : L.fdi[c == 2 ? r : s]);
-                dL += (is_m ? 1.0 : -1.0) * (c_fnew - c_fold);
+            {
+                const double d_fold = c < 2 ? fdo_c : fdi_c;
+                if constexpr (GS == 4) {
+                    dL += act ? (c_fnew - fm_c) - (d_fnew - d_fold) : 0.0;
+                } else {
+                    const double c_fold = is_m ? fm_c : d_fold;
+                    dL += act ? (is_m ? 1.0 : -1.0) * (c_fnew - c_fold) : 0.0;
+                }
             }
             // Hastings terms of t = r and t = s (lanes 0-3): before, after;
             // every lane evaluates, lanes 4-7 and idle vertices add zero
             {
-                const int Mrr = L.Ms[r * RS + r], Mrs = L.Ms[r * RS + s], Msr = L.Ms[s * RS + r], Mss = L.Ms[s * RS + s];
                 const int drr = -ko_r - ki_r - ell, drs = -ko_s + ki_r, dsr = ko_r - ki_s;
                 const int kk = c == 0 ? ko_r + ki_r + 2 * ell : c == 1 ? ko_s + ki_s : c == 2 ? ko_r + ki_r : ko_s + ki_s + 2 * ell;
                 const int num = c == 0 ? Mrs + Msr : c == 1 ? 2 * Mss : c == 2 ? 2 * (Mrr + drr) : Msr + dsr + Mrs + drs;
-                const int den = c == 0 ? L.dsum[r] : c == 1 ? L.dsum[s] : c == 2 ? L.dsum[r] - k : L.dsum[s] + k;
+                const int den = c == 0 ? dsr_ : c == 1 ? dss_ : c == 2 ? dsr_ - k : dss_ + k;
                 const double term = (double)kk * (((double)num + eps) / ((double)den + epsC));
-                const bool use = act && gl < 4 && kk != 0;
-                qf += use && c < 2 ? term : 0.0;
-                qr += use && c >= 2 ? term : 0.0;
+                const bool use = act & is_m & (kk != 0);
+                qf += (use & (c < 2)) ? term : 0.0;
+                qr += (use & (c >= 2)) ? term : 0.0;
             }
-            dL = grp8_sum(dL);
-            qf = grp8_sum(qf);
-            qr = grp8_sum(qr);
+            dL = grp_sum<GS>(dL);
+            qf = grp_sum<GS>(qf);
+            qr = grp_sum<GS>(qr);
             // the three logs of the wave's 64/GS vertices in one evaluation
             double lg;
             {
@@ -826,7 +876,7 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
 }
 
 template <bool ENDS, bool TRACE, int CM>
-__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTraceDev tr) {
+__global__ void __launch_bounds__(EVAL_T) __attribute__((amdgpu_waves_per_eu(EvalLds<CM>::WAVES))) k_dense_eval(EvalArgs a, SweepTraceDev tr) {
     __shared__ EvalLds<CM> L;
     eval_body<ENDS, TRACE, CM>(L, a, tr, StridedChunks{(int)blockIdx.x, (int)gridDim.x, 0});
 }
@@ -840,7 +890,7 @@ __global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval(EvalArgs a, SweepTrace
 // graph.  Decisions are ints (the labels are gathered, no end bytes), no
 // statistics and no trace.
 template <int CM>
-__global__ void __launch_bounds__(EVAL_T, 4) k_dense_eval_multi(const EvalArgs *__restrict__ A,
+__global__ void __launch_bounds__(EVAL_T) __attribute__((amdgpu_waves_per_eu(EvalLds<CM>::WAVES))) k_dense_eval_multi(const EvalArgs *__restrict__ A,
                                                                const int *__restrict__ nruns,
                                                                const int *__restrict__ gstart, int *__restrict__ ctr,
                                                                int D, int run_len) {
@@ -909,7 +959,7 @@ __global__ void __launch_bounds__(256) k_to_dense(const ToDense *__restrict__ J,
 // delta, flushed with integer atomics); every end byte takes the far end's new
 // block; the labels of the chunk's vertices take their decisions.  The
 // decisions are read from nb (never from the labels being rewritten), so the
-// workgroups need no ordering.  A thread takes SEG consecutive ends of the
+// workgroups need no ordering.  A thread takes 8 consecutive ends of the
 // chunk (its out-ends, then its in-ends) and issues all their loads and
 // decision gathers before any use.
 constexpr int CHU = 256;     // vertices per chunk of the update

@@ -112,15 +112,15 @@ __device__ __forceinline__ double grp8_sum(double x) {
     return x;
 }
 
-// Sum over an aligned group of GS = 8, 16 or 32 lanes: pairs, quads, the
-// mirrored half row, the mirrored row (16, 32), then the neighbouring row (32).
-// Each step adds the same two values on every lane (in either order), so the
-// whole group ends with one identical sum.
+// Sum over an aligned group of GS = 4, 8, 16 or 32 lanes: pairs, quads, the
+// mirrored half row (8 and more), the mirrored row (16, 32), then the
+// neighbouring row (32).  Each step adds the same two values on every lane (in
+// either order), so the whole group ends with one identical sum.
 template <int GS>
 __device__ __forceinline__ double grp_sum(double x) {
     x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
     x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
-    x += dpp_f64<0x141>(x);  // row_half_mirror
+    if (GS >= 8) x += dpp_f64<0x141>(x);  // row_half_mirror
     if (GS >= 16) x += dpp_f64<0x140>(x);  // row_mirror
     if (GS >= 32) x += __shfl_xor(x, 16, 64);
     return x;
@@ -129,7 +129,7 @@ template <int GS>
 __device__ __forceinline__ int grp_sum_i32(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
+    if (GS >= 8) x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);
     if (GS >= 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false);
     if (GS >= 32) x += __shfl_xor(x, 16, 64);
     return x;
