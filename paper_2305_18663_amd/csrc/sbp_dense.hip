@@ -962,8 +962,9 @@ __global__ void __launch_bounds__(256) k_to_dense(const ToDense *__restrict__ J,
 // workgroups need no ordering.  A thread takes 8 consecutive ends of the
 // chunk (its out-ends, then its in-ends) and issues all their loads and
 // decision gathers before any use.
-constexpr int CHU = 256;     // vertices per chunk of the update
+constexpr int CHU = 512;     // vertices per chunk of the update
 constexpr int UPD_T = 1024;  // threads per update workgroup, one workgroup per CU
+static_assert(CHU < UPD_T, "a chunk's range ends are loaded by thread nv");
 // A thread takes an 8-aligned block of 8 consecutive end positions of the
 // chunk (its out-ends, then its in-ends): with VEC (16-byte aligned id
 // arrays) the ids come in two 16-byte loads, the end bytes in one 8-byte load
@@ -1096,33 +1097,46 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
         const int o0 = op[0], o1 = op[nv], i0 = ip[0], i1 = ip[nv];
         const int bo0 = o0 >> 3, nbo = o1 > o0 ? ((o1 + 7) >> 3) - bo0 : 0;
         const int bi0 = i0 >> 3, nbi = i1 > i0 ? ((i1 + 7) >> 3) - bi0 : 0;
-        for (int rr = tid; rr < nbo + nbi; rr += UPD_T) {
-            const bool out = rr < nbo;
-            const int p0 = (out ? bo0 + rr : bi0 + (rr - nbo)) * 8;
-            const int lo = out ? o0 : i0, hi = out ? o1 : i1;
-            const int *__restrict__ idx = out ? g.out_idx : g.in_idx;
-            unsigned char *__restrict__ nlp = out ? nlo : nli;
+        const int nbt = nbo + nbi;
+        // Block rr of the chunk: its first position, run and owner array.
+        // Ids, end bytes and the far ends' decisions of a thread's two blocks
+        // are all loaded before either block is counted.
+        struct Blk {
+            bool out;
+            int p0, lo, hi;
+            unsigned b[8], x[8];
+        };
+        auto load_blk = [&](int rr, bool mine, Blk &k) {
+            k.out = rr < nbo;
+            k.p0 = (k.out ? bo0 + rr : bi0 + (rr - nbo)) * 8;
+            k.lo = k.out ? o0 : i0;
+            k.hi = k.out ? o1 : i1;
+            const int *__restrict__ idx = k.out ? g.out_idx : g.in_idx;
+            const unsigned char *__restrict__ nlp = k.out ? nlo : nli;
             int u[8];
-            if (VEC && p0 + 8 <= g.e) {
-                const int4 A = *(const int4 *)(idx + p0), B = *(const int4 *)(idx + p0 + 4);
+            if (VEC && k.p0 + 8 <= g.e) {
+                const int4 A = *(const int4 *)(idx + k.p0), B = *(const int4 *)(idx + k.p0 + 4);
                 u[0] = A.x; u[1] = A.y; u[2] = A.z; u[3] = A.w;
                 u[4] = B.x; u[5] = B.y; u[6] = B.z; u[7] = B.w;
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) u[q] = (p0 + q >= lo && p0 + q < hi) ? idx[p0 + q] : 0;
+                for (int q = 0; q < 8; ++q) u[q] = (k.p0 + q >= k.lo && k.p0 + q < k.hi) ? idx[k.p0 + q] : 0;
             }
-            const uint2 bw = *(const uint2 *)(nlp + p0);
-            unsigned b[8], x[8];
+            const uint2 bw = *(const uint2 *)(nlp + k.p0);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const bool in_run = p0 + q >= lo && p0 + q < hi;
-                b[q] = in_run ? (((q < 4 ? bw.x : bw.y) >> (8 * (q & 3))) & 0xffu) : 0x100u;  // 0x100: not ours
+                const bool in_run = mine && k.p0 + q >= k.lo && k.p0 + q < k.hi;
+                k.b[q] = in_run ? (((q < 4 ? bw.x : bw.y) >> (8 * (q & 3))) & 0xffu) : 0x100u;  // 0x100: not ours
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = b[q] < 0xffu ? (u[q] < sl ? (unsigned)nbs[u[q]] : (unsigned)nb[u[q]]) : 0xffu;
+            for (int q = 0; q < 8; ++q)
+                k.x[q] = k.b[q] < 0xffu ? (u[q] < sl ? (unsigned)nbs[u[q]] : (unsigned)nb[u[q]]) : 0xffu;
+        };
+        auto count_blk = [&](const Blk &k) {
+            unsigned char *__restrict__ nlp = k.out ? nlo : nli;
             int w = 0, nxt = 0;
-            if (out) {  // owner of the first position of the block in the chunk, then a forward walk
-                const int pf = max(lo, p0);
+            if (k.out) {  // owner of the first position of the block in the chunk, then a forward walk
+                const int pf = max(k.lo, k.p0);
                 int l = 0, h = nv - 1;
                 while (l < h) {
                     const int mid = (l + h + 1) >> 1;
@@ -1133,19 +1147,28 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                if (b[q] == 0x100u) continue;
-                const unsigned bn = x[q] != 0xffu ? x[q] : b[q];
-                if (bn != b[q]) nlp[p0 + q] = (unsigned char)bn;
-                if (!out) continue;
-                while (p0 + q >= nxt) nxt = op[++w + 1];
+                if (k.b[q] == 0x100u) continue;
+                const unsigned bn = k.x[q] != 0xffu ? k.x[q] : k.b[q];
+                if (bn != k.b[q]) nlp[k.p0 + q] = (unsigned char)bn;
+                if (!k.out) continue;
+                while (k.p0 + q >= nxt) nxt = op[++w + 1];
                 const int va = a0[w], vb = a1[w];
-                const int ua = b[q] == 0xffu ? va : (int)b[q];  // a self-loop's far end is the vertex
-                const int ub = b[q] == 0xffu ? vb : (int)bn;
+                const int ua = k.b[q] == 0xffu ? va : (int)k.b[q];  // a self-loop's far end is the vertex
+                const int ub = k.b[q] == 0xffu ? vb : (int)bn;
                 if (va != vb || ua != ub) {
                     atomicAdd(&dl[va * C + ua], -1);
                     atomicAdd(&dl[vb * C + ub], 1);
                 }
             }
+        };
+        for (int rr = tid; rr < nbt; rr += 2 * UPD_T) {
+            const int rr2 = rr + UPD_T;
+            const bool two = rr2 < nbt;
+            Blk k1, k2;
+            load_blk(rr, true, k1);
+            load_blk(two ? rr2 : rr, two, k2);  // without a second block: the first again, nothing of it counted
+            count_blk(k1);
+            if (two) count_blk(k2);
         }
     }
     __syncthreads();
