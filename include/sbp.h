@@ -392,7 +392,8 @@ int sbp_engine_destroy(sbp_engine *eng);
 
 /* Launch-shape tuning (results do not depend on it).  Keys:
  *   "dense_eval_workgroups"  workgroups of the dense sweep-evaluation grid
- *                            (0 = one per 64-vertex chunk, capped at 4 per CU)
+ *                            (0 = one per chunk, capped at the workgroups
+ *                            a CU holds)
  *   "dense_delta_workgroups" workgroups of the dense block-matrix update
  *   "dense_update_moved_share" a one-batch dense sweep updates M and the end
  *                            bytes from the moved vertices alone when at
@@ -406,6 +407,10 @@ int sbp_engine_destroy(sbp_engine *eng);
  *   "table_build"            engine steps count M into the tables: 0 never,
  *                            1 when the tables are small against the edges
  *                            (default), 2 whenever every graph's table fits
+ *   "batches_in_step"        1 (default): the hubs and batches of a sweep after
+ *                            its first run in the same engine step, each on a
+ *                            blockmodel rebuilt after the one before, without
+ *                            a host round trip; 0: one a step
  * Returns SBP_E_ARG for an unknown key or a value out of range. */
 int sbp_tune(const char *key, int64_t value);
 

@@ -329,6 +329,7 @@ int g_engine_dense_max_c = SBP_DENSE_MAX_C;  // engine sweeps at C <= this use t
 int g_table_max_c = SBP_TABLE_MAX_C;         // sparse sweeps at C <= this read M from a lookup table (0: never)
 int g_table_ratio = 4;  // automatic table builds need ratio * cost <= 16 * edges (4: cost <= 4 E)
 int g_table_build = 1;  // count M into the tables: 0 never, 1 when they are small against the edges, 2 whenever all fit
+int g_batches_in_step = 1;  // a sweep's later hubs and batches run in the step of its first (0: one a step)
 
 UnionLayout union_layout(Arena &a, long long N, long long E, int G) {
     UnionLayout u{};
@@ -959,21 +960,25 @@ GDev desc_of(const GraphRun &r) {
     return d;
 }
 
-int engine_step(sbp_engine *eng, int *active_out) {
+// Layout, lookup tables and union blockmodel of the given graphs for one
+// round of actions (descriptors without actions); with_dl: their DLs too.
+struct StepState {
+    std::vector<GDev> hG;
+    HostMeta hm;
+    std::vector<int *> tab;
+    SparseBM bm;
+};
+int step_build(sbp_engine *eng, const std::vector<GraphRun *> &runs, StepState &st, bool with_dl) {
     hipStream_t s = eng->s;
     UnionLayout &u = eng->u;
-    const int G = (int)eng->active.size();
-    if (G == 0) {
-        if (active_out) *active_out = 0;
-        return 0;
-    }
+    const int G = (int)runs.size();
     int rc;
-    // 1-3: layout, counts, rebuild, DL
-    std::vector<GDev> hG(G);
+    std::vector<GDev> &hG = st.hG;
+    hG.assign(G, GDev{});
     // lookup tables of M for the graphs whose count (an upper bound: a merge
     // of the last step may have lowered it on the device) allows one, while
     // the space lasts; tables change no result, only the lookups' cost
-    std::vector<int *> tab(G, nullptr);
+    st.tab.assign(G, nullptr);
     std::vector<int> tlist;
     long long tused = 0;
     bool all_tabled = g_table_build > 0;  // every graph gets a table: M is counted into them
@@ -989,7 +994,7 @@ int engine_step(sbp_engine *eng, int *active_out) {
         long long need = 0, cost = 0, edges = 0;
         bool spread = true;
         for (int g = 0; g < G && all_tabled; ++g) {
-            const long long Cb = eng->active[g]->C, e = eng->active[g]->g.e;
+            const long long Cb = runs[g]->C, e = runs[g]->g.e;
             all_tabled = Cb <= g_table_max_c;
             need += (Cb * Cb + 63) & ~63LL;
             cost += Cb * Cb * (Cb > 512 ? 4 : 1);
@@ -1000,56 +1005,55 @@ int engine_step(sbp_engine *eng, int *active_out) {
         all_tabled = all_tabled && need <= u.table_ints && (g_table_build == 2 || cheap);
     }
     for (int g = 0; g < G; ++g) {
-        hG[g] = desc_of(*eng->active[g]);
+        hG[g] = desc_of(*runs[g]);
         hG[g].action = ACT_NONE;
         const long long Cb = hG[g].C;
         if (all_tabled ||
             (Cb <= g_table_max_c && Cb > g_engine_dense_max_c && Cb * Cb <= u.table_ints - tused)) {
-            tab[g] = u.tables + tused;
+            st.tab[g] = u.tables + tused;
             tused += (Cb * Cb + 63) & ~63LL;
-            hG[g].mdense = tab[g];
+            hG[g].mdense = st.tab[g];
             tlist.push_back(g);
         }
     }
-    HostMeta hm;
-    plan_step(hG, hm);
-    if ((rc = upload_step(hG, hm, u, s))) return rc;
+    plan_step(hG, st.hm);
+    if ((rc = upload_step(hG, st.hm, u, s))) return rc;
     if (!tlist.empty())
         SBP_HIP_CHECK(hipMemcpyAsync(u.tlist, tlist.data(), tlist.size() * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fix_C, dim3((G + 63) / 64), dim3(64), 0, s, u.dG, G, (const int *)u.Cdev);
     SBP_LAUNCH_CHECK();
-    SparseBM bm = u.bm;
+    st.bm = u.bm;
     if (all_tabled) {
-        if ((rc = build_union_from_tables(u.dG, hm.m, bm, u.ws, u.tlist, G, s))) return rc;
+        if ((rc = build_union_from_tables(u.dG, st.hm.m, st.bm, u.ws, u.tlist, G, s))) return rc;
     } else {
-        if ((rc = build_union_sparse(u.dG, hm.m, bm, u.ws, s))) return rc;
-        if ((rc = union_lookup_tables(u.dG, G, (int)tlist.size(), bm, s))) return rc;
+        if ((rc = build_union_sparse(u.dG, st.hm.m, st.bm, u.ws, s))) return rc;
+        if ((rc = union_lookup_tables(u.dG, G, (int)tlist.size(), st.bm, s))) return rc;
     }
-    if ((rc = union_dl(u.dG, hm.m, bm, u.ws, s))) return rc;
-    // 4: read back
-    eng->h_dl.resize(G);
-    eng->h_C.resize(G);
-    SBP_HIP_CHECK(hipMemcpyAsync(eng->h_dl.data(), u.ws.dl, G * sizeof(double), hipMemcpyDeviceToHost, s));
-    std::vector<int> cd(eng->maxG);
-    SBP_HIP_CHECK(hipMemcpyAsync(cd.data(), u.Cdev, eng->maxG * sizeof(int), hipMemcpyDeviceToHost, s));
-    SBP_HIP_CHECK(hipStreamSynchronize(s));
-    // 5: advance every graph
-    for (int g = 0; g < G; ++g) {
-        GraphRun &r = *eng->active[g];
-        advance(eng, r, eng->h_dl[g], cd[r.eslot]);
-    }
-    // 6: actions against the blockmodel built above (same layout)
+    if (with_dl && (rc = union_dl(u.dG, st.hm.m, st.bm, u.ws, s))) return rc;
+    return 0;
+}
+
+// The actions the given graphs hold (GraphRun::action) against the blockmodel
+// step_build made for the same list.
+int step_act(sbp_engine *eng, const std::vector<GraphRun *> &runs, StepState &st) {
+    hipStream_t s = eng->s;
+    UnionLayout &u = eng->u;
+    const int G = (int)runs.size();
+    int rc;
+    std::vector<GDev> &hG = st.hG;
+    const HostMeta &hm = st.hm;
+    SparseBM &bm = st.bm;
     bool any_act = false;
     std::vector<DenseSweepJob> djobs;
     for (int g = 0; g < G; ++g) {
-        GraphRun &r = *eng->active[g];
+        GraphRun &r = *runs[g];
         GDev d = desc_of(r);
         d.voff = hG[g].voff;
         d.boff = hG[g].boff;
         d.eoff = hG[g].eoff;
         d.C = r.C;
         if (r.action == ACT_MERGE) d.C = r.C0;
-        d.mdense = tab[g];  // filled for the count the build used, which the actions keep
+        d.mdense = st.tab[g];  // filled for the count the build used, which the actions keep
         if (r.action == ACT_SWEEP && d.C <= g_engine_dense_max_c) {
             // the dense kernels evaluate it; the union kernels apply it
             d.action = ACT_DSWEEP;
@@ -1066,43 +1070,102 @@ int engine_step(sbp_engine *eng, int *active_out) {
         hG[g] = d;
         any_act |= r.action != ACT_NONE;
     }
-    if (any_act) {
-        // work lists for this step's actions (layout offsets kept from the build)
-        HostMeta am;
-        std::vector<GDev> tmp = hG;
-        plan_step(tmp, am);
-        for (int g = 0; g < G; ++g) am.arr(0)[g] = hm.arr(0)[g], am.arr(1)[g] = hm.arr(1)[g];
-        am.m.Ctot = hm.m.Ctot;
-        am.m.n_chunks = hm.m.n_chunks;
-        if ((rc = upload_step(hG, am, u, s))) return rc;
-        SweepTraceDev tr{};
-        if (!djobs.empty() &&
-            (rc = dense_multi_sweep(djobs, bm, u.ftab, u.ftab_max, u.dmulti, eng->maxG, s)))
-            return rc;
-        if (am.m.n_leaf + am.m.n_hub > 0 || !djobs.empty()) {
-            StepMeta sm = am.m;
-            sm.leaf = am.m.leaf;
-            if ((rc = union_sweep(u.dG, sm, bm, u.ws, tr, s))) return rc;
+    if (!any_act) return 0;
+    // work lists for this round's actions (layout offsets kept from the build)
+    HostMeta am;
+    std::vector<GDev> tmp = hG;
+    plan_step(tmp, am);
+    for (int g = 0; g < G; ++g) am.arr(0)[g] = st.hm.arr(0)[g], am.arr(1)[g] = st.hm.arr(1)[g];
+    am.m.Ctot = hm.m.Ctot;
+    am.m.n_chunks = hm.m.n_chunks;
+    if ((rc = upload_step(hG, am, u, s))) return rc;
+    SweepTraceDev tr{};
+    if (!djobs.empty() &&
+        (rc = dense_multi_sweep(djobs, bm, u.ftab, u.ftab_max, u.dmulti, eng->maxG, s)))
+        return rc;
+    if (am.m.n_leaf + am.m.n_hub > 0 || !djobs.empty()) {
+        StepMeta sm = am.m;
+        sm.leaf = am.m.leaf;
+        if ((rc = union_sweep(u.dG, sm, bm, u.ws, tr, s))) return rc;
+    }
+    if (am.m.n_mblk > 0) {
+        if ((rc = union_merge_scores(u.dG, am.m, bm, u.partner, u.dS, u.dSl, s))) return rc;
+        if ((rc = union_merge_apply(u.dG, am.m, u.partner, u.dSl, u.ws, s))) return rc;
+        if ((rc = union_relabel(u.dG, G, am.m.mvtx, am.m.n_mvtx, am.m.mblk, u.ws.mmap, s))) return rc;
+        hipLaunchKernelGGL(k_store_C, dim3((G + 63) / 64), dim3(64), 0, s, (const GDev *)u.dG, G, (int)ACT_MERGE,
+                           (const int *)u.ws.gC, u.Cdev);
+        SBP_LAUNCH_CHECK();
+    }
+    if (am.m.n_cblk > 0) {
+        if ((rc = union_compact(u.dG, am.m, u.ws, s))) return rc;
+        if ((rc = union_relabel(u.dG, G, am.m.cvtx, am.m.n_cvtx, am.m.cblk, u.ws.mmap, s))) return rc;
+        hipLaunchKernelGGL(k_store_C, dim3((G + 63) / 64), dim3(64), 0, s, (const GDev *)u.dG, G, (int)ACT_COMPACT,
+                           (const int *)u.ws.gC, u.Cdev);
+        SBP_LAUNCH_CHECK();
+    }
+    for (int g = 0; g < G; ++g) {
+        GraphRun &r = *runs[g];
+        if (r.action == ACT_MERGE) ++r.phase_ctr;
+    }
+    return 0;
+}
+
+// The graph's sweep goes on in the same step when what comes next in it is
+// another hub or batch: that needs only the blockmodel after the one before,
+// no host decision.  Takes the step (as advance would) and returns true.
+bool continue_sweep(GraphRun &r) {
+    if (!g_batches_in_step || r.phase != GraphRun::MCMC || r.action != ACT_SWEEP) return false;
+    if (r.hub_i >= 0) {  // the next hub, else the first batch
+        if (++r.hub_i >= r.nh) {
+            r.hub_i = -1;
+            r.batch = 0;
         }
-        if (am.m.n_mblk > 0) {
-            if ((rc = union_merge_scores(u.dG, am.m, bm, u.partner, u.dS, u.dSl, s))) return rc;
-            if ((rc = union_merge_apply(u.dG, am.m, u.partner, u.dSl, u.ws, s))) return rc;
-            if ((rc = union_relabel(u.dG, G, am.m.mvtx, am.m.n_mvtx, am.m.mblk, u.ws.mmap, s))) return rc;
-            hipLaunchKernelGGL(k_store_C, dim3((G + 63) / 64), dim3(64), 0, s, (const GDev *)u.dG, G, (int)ACT_MERGE,
-                               (const int *)u.ws.gC, u.Cdev);
-            SBP_LAUNCH_CHECK();
-        }
-        if (am.m.n_cblk > 0) {
-            if ((rc = union_compact(u.dG, am.m, u.ws, s))) return rc;
-            if ((rc = union_relabel(u.dG, G, am.m.cvtx, am.m.n_cvtx, am.m.cblk, u.ws.mmap, s))) return rc;
-            hipLaunchKernelGGL(k_store_C, dim3((G + 63) / 64), dim3(64), 0, s, (const GDev *)u.dG, G, (int)ACT_COMPACT,
-                               (const int *)u.ws.gC, u.Cdev);
-            SBP_LAUNCH_CHECK();
-        }
-        for (int g = 0; g < G; ++g) {
-            GraphRun &r = *eng->active[g];
-            if (r.action == ACT_MERGE) ++r.phase_ctr;
-        }
+        return true;
+    }
+    const int nb = std::max(1, std::min(r.p.n_batches, r.g.n));
+    if (r.batch + 1 < nb) {
+        ++r.batch;
+        return true;
+    }
+    return false;
+}
+
+int engine_step(sbp_engine *eng, int *active_out) {
+    hipStream_t s = eng->s;
+    UnionLayout &u = eng->u;
+    const int G = (int)eng->active.size();
+    if (G == 0) {
+        if (active_out) *active_out = 0;
+        return 0;
+    }
+    int rc;
+    // 1-3: layout, counts, rebuild, DL
+    StepState st;
+    if ((rc = step_build(eng, eng->active, st, true))) return rc;
+    // 4: read back
+    eng->h_dl.resize(G);
+    eng->h_C.resize(G);
+    SBP_HIP_CHECK(hipMemcpyAsync(eng->h_dl.data(), u.ws.dl, G * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<int> cd(eng->maxG);
+    SBP_HIP_CHECK(hipMemcpyAsync(cd.data(), u.Cdev, eng->maxG * sizeof(int), hipMemcpyDeviceToHost, s));
+    SBP_HIP_CHECK(hipStreamSynchronize(s));
+    // 5: advance every graph
+    for (int g = 0; g < G; ++g) {
+        GraphRun &r = *eng->active[g];
+        advance(eng, r, eng->h_dl[g], cd[r.eslot]);
+    }
+    // 6: actions against the blockmodel built above (same layout)
+    if ((rc = step_act(eng, eng->active, st))) return rc;
+    // 7: the further hubs and batches of the sweeps this step began, each
+    // against a blockmodel rebuilt after the one before, with no host round trip
+    for (;;) {
+        std::vector<GraphRun *> more;
+        for (GraphRun *r : eng->active)
+            if (continue_sweep(*r)) more.push_back(r);
+        if (more.empty()) break;
+        StepState st2;
+        if ((rc = step_build(eng, more, st2, false))) return rc;
+        if ((rc = step_act(eng, more, st2))) return rc;
     }
     // host copy of block counts for graphs that loaded a stored assignment
     for (int g = 0; g < G; ++g) {
@@ -1763,6 +1826,10 @@ int sbp_tune(const char *key, int64_t value) {
     }
     if (!strcmp(key, "table_build") && value >= 0 && value <= 2) {
         g_table_build = (int)value;
+        return 0;
+    }
+    if (!strcmp(key, "batches_in_step") && (value == 0 || value == 1)) {
+        g_batches_in_step = (int)value;
         return 0;
     }
     if (dense_tune(key, (long long)value) == 0) return 0;

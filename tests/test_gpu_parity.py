@@ -643,6 +643,28 @@ def test_engine_dense_sweeps_equal_sparse_sweeps(n_batches):
         assert np.array_equal(a["trace"], b["trace"])
 
 
+@pytest.mark.parametrize("kw", [dict(n_batches=3), dict(n_batches=2, n_hubs=6), dict(n_batches=1, n_hubs=3)])
+def test_batches_in_step_change_nothing(kw):
+    # the later hubs and batches of a sweep run inside the engine step that
+    # began it (rebuilt blockmodel, no host round trip); one a step gives the
+    # same partitions, bit for bit
+    sizes = [400, 2500, 900, 6000]
+    graphs = [gen.batch_graph(n, seed=3700 + i) for i, n in enumerate(sizes)]
+    dgs = [sbp.DeviceGraph(g) for g in graphs]
+    kws = [dict(seed=710 + i, **kw) for i in range(len(graphs))]
+    out = []
+    try:
+        for mode in (1, 0):
+            sbp.sbp_tune("batches_in_step", mode)
+            out.append(sbp.sbp_partition_batch(dgs, kws))
+    finally:
+        sbp.sbp_tune("batches_in_step", 1)
+    for a, b in zip(*out):
+        assert a["C"] == b["C"] and a["dl"] == b["dl"]
+        assert np.array_equal(a["lab"], b["lab"])
+        assert np.array_equal(a["trace"], b["trace"])
+
+
 def test_lookup_tables_change_nothing():
     # sparse-tier sweeps read M from a C x C table when C <= 2048; with the
     # tables switched off (binary searches of the rows) every result is equal
