@@ -100,7 +100,9 @@ typedef struct sbp_sweep_stats {
     int64_t proposals;       /* vertices evaluated */
     int64_t self_proposals;  /* proposals of the vertex's own block (no-ops) */
     int64_t accepted;
-    int64_t reserved;
+    int64_t near_ties;       /* proposals (not no-ops) whose margin (see the
+                              * trace) is within 1e-9 of zero: decisions a
+                              * differently ordered FP64 sum could flip */
     double sum_dS_accepted;  /* sum of DL changes of accepted moves */
     double dl_after;         /* DL of the assignment after the sweep */
 } sbp_sweep_stats;

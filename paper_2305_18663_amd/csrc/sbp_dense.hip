@@ -214,23 +214,25 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
     }
     __shared__ int so[DC], si[DC];
     __shared__ double wred[FIN_T / 64], sred[FIN_T / 64];
-    __shared__ long long lred[3][FIN_T / 64];
+    __shared__ long long lred[4][FIN_T / 64];
     const int C = g.C, CC = C * C, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double *tab = bm.ftab;
     const unsigned fmax = bm.ftab_max;
-    long long a0 = 0, a1 = 0, a2 = 0;
+    long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     double sd = 0.0;
     if (stats) {
         for (int w = tid; w < nwg; w += FIN_T) {
             a0 += stats_part[4 * w + 0];
             a1 += stats_part[4 * w + 1];
             a2 += stats_part[4 * w + 2];
+            a3 += stats_part[4 * w + 3];
             sd += sum_part[w];
         }
         if (extra >= 0 && tid == 0) {  // the sequential pass's totals
             a0 += stats_part[4 * extra + 0];
             a1 += stats_part[4 * extra + 1];
             a2 += stats_part[4 * extra + 2];
+            a3 += stats_part[4 * extra + 3];
             sd += sum_part[extra];
         }
     }
@@ -267,23 +269,26 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
     a0 = wave_sum_i64(a0);
     a1 = wave_sum_i64(a1);
     a2 = wave_sum_i64(a2);
+    a3 = wave_sum_i64(a3);
     sd = wave_sum(sd);
     if (lane == 0) {
         wred[wv] = acc;
         lred[0][wv] = a0;
         lred[1][wv] = a1;
         lred[2][wv] = a2;
+        lred[3][wv] = a3;
         sred[wv] = sd;
     }
     __syncthreads();
     if (tid == 0) {
         double L = 0.0, sdt = 0.0;
-        long long p = 0, sp = 0, ac = 0;
+        long long p = 0, sp = 0, ac = 0, ti = 0;
         for (int w = 0; w < FIN_T / 64; ++w) {
             L += wred[w];
             p += lred[0][w];
             sp += lred[1][w];
             ac += lred[2][w];
+            ti += lred[3][w];
             sdt += sred[w];
         }
         const double dl = model_terms_d((double)g.e, (double)g.n, (double)C) - L;
@@ -293,7 +298,7 @@ __global__ void __launch_bounds__(FIN_T) k_dense_final(GDev g, DenseBM bm, int *
             stats->proposals = (first ? 0 : stats->proposals) + p;
             stats->self_proposals = (first ? 0 : stats->self_proposals) + sp;
             stats->accepted = (first ? 0 : stats->accepted) + ac;
-            stats->reserved = first ? 0 : stats->reserved;
+            stats->near_ties = (first ? 0 : stats->near_ties) + ti;
             stats->sum_dS_accepted = (first ? 0.0 : stats->sum_dS_accepted) + sdt;
             stats->dl_after = dl;
         }
@@ -358,7 +363,7 @@ struct EvalLds {
     double fM[CM * RS];
     double fdo[CM], fdi[CM], inv[CM];
     uint64_t W[4][CH];  // Philox words 0-3 of the chunk's vertices
-    long long wst[3 * (EVAL_T / 64)];
+    long long wst[4 * (EVAL_T / 64)];
     double wsd[EVAL_T / 64];
     int Ms[CM * RS];
     int dsum[CM], dos[CM], dis[CM];
@@ -465,6 +470,7 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
         L.inv[tid] = 1.0 / ((double)(o + n) + epsC);
     }
     long long n_prop = 0, n_self = 0, n_acc = 0;
+    int n_tie = 0;
     double s_dS = 0.0;
     const unsigned sweep = a.sweep_dev ? *a.sweep_dev : a.sweep;
     const int nbc = (a.n - a.batch + a.n_batches - 1) / a.n_batches;
@@ -822,6 +828,7 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
             const double lnH = (act && k > 0) ? lnqr - lnqf : 0.0;
             const double z = -a.beta * dS + lnH;
             const bool acc = act && lnu < z;
+            const bool tie = act && fabs(z - lnu) < SBP_NEAR_TIE;
             if (gl == 0 && valid) {
                 if (!hub) {
                     ++n_prop;
@@ -831,6 +838,7 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
                     ++n_acc;
                     s_dS += dS;
                 }
+                n_tie += tie ? 1 : 0;
                 if constexpr (ENDS) ((unsigned char *)a.nb)[v] = acc ? (unsigned char)s : 0xffu;
                 else ((int *)a.nb)[v] = acc ? s : -1;
                 if constexpr (TRACE) if (!hub) {
@@ -840,7 +848,8 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
                     if (tr.lnH) tr.lnH[uu] = act ? lnH : 0.0;
                     if (tr.margin) tr.margin[uu] = act ? z - lnu : 0.0;
                     if (tr.accept) tr.accept[uu] = acc ? 1 : 0;
-                    if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) : -1;
+                    // -1 no-op, else accepted (bit 0) and near tie (bit 1)
+                    if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) + (tie ? 2 : 0) : -1;
                 }
             }
         }
@@ -849,28 +858,31 @@ __device__ __forceinline__ void eval_body(EvalLds<CM> &L, const EvalArgs &a, con
     n_prop = wave_sum_i64(n_prop);
     n_self = wave_sum_i64(n_self);
     n_acc = wave_sum_i64(n_acc);
+    n_tie = wave_sum_i32(n_tie);
     s_dS = wave_sum(s_dS);
     __syncthreads();
     if (lane == 0) {
-        L.wst[3 * wv + 0] = n_prop;
-        L.wst[3 * wv + 1] = n_self;
-        L.wst[3 * wv + 2] = n_acc;
+        L.wst[4 * wv + 0] = n_prop;
+        L.wst[4 * wv + 1] = n_self;
+        L.wst[4 * wv + 2] = n_acc;
+        L.wst[4 * wv + 3] = n_tie;
         L.wsd[wv] = s_dS;
     }
     __syncthreads();
     if (tid == 0) {
-        long long p = 0, sp = 0, ac = 0;
+        long long p = 0, sp = 0, ac = 0, ti = 0;
         double sd = 0.0;
         for (int w = 0; w < EVAL_T / 64; ++w) {
-            p += L.wst[3 * w + 0];
-            sp += L.wst[3 * w + 1];
-            ac += L.wst[3 * w + 2];
+            p += L.wst[4 * w + 0];
+            sp += L.wst[4 * w + 1];
+            ac += L.wst[4 * w + 2];
+            ti += L.wst[4 * w + 3];
             sd += L.wsd[w];
         }
         a.stats_part[4 * blockIdx.x + 0] = p;
         a.stats_part[4 * blockIdx.x + 1] = sp;
         a.stats_part[4 * blockIdx.x + 2] = ac;
-        a.stats_part[4 * blockIdx.x + 3] = 0;
+        a.stats_part[4 * blockIdx.x + 3] = ti;
         a.sum_part[blockIdx.x] = sd;
     }
 }
@@ -1397,7 +1409,7 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
         dis[tid] = bm.din[tid];
     }
     for (int i = tid; i < nh; i += HUBS_T) hl[i] = g.lab[order[i]];
-    long long n_prop = 0, n_self = 0, n_acc = 0;
+    long long n_prop = 0, n_self = 0, n_acc = 0, n_tie = 0;
     double s_dS = 0.0;
     // hub i's meta and ends; hub i + 1's meta
     int v = order[0], kv = kk[0], h0 = hoff[0];
@@ -1557,19 +1569,21 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
                 acc = lnu < z;
             }
             if (lane == 0) {
+                const bool tie = act && fabs(z - lnu) < SBP_NEAR_TIE;
                 ++n_prop;
                 if (!act) ++n_self;
                 if (acc) {
                     ++n_acc;
                     s_dS += dS;
                 }
+                n_tie += tie ? 1 : 0;
                 const int uu = g.voff + v;
                 if (tr.prop) tr.prop[uu] = s;
                 if (tr.dS) tr.dS[uu] = dS;
                 if (tr.lnH) tr.lnH[uu] = lnH;
                 if (tr.margin) tr.margin[uu] = act ? z - lnu : 0.0;
                 if (tr.accept) tr.accept[uu] = acc ? 1 : 0;
-                if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) : -1;
+                if (tr.status) tr.status[uu] = act ? (acc ? 1 : 0) + (tie ? 2 : 0) : -1;
                 s_dec = acc ? s : -1;
             }
         }
@@ -1637,7 +1651,7 @@ __global__ void __launch_bounds__(HUBS_T) k_dense_hubs(GDev g, DenseBM bm, const
         stats_part[4 * slot + 0] = n_prop;
         stats_part[4 * slot + 1] = n_self;
         stats_part[4 * slot + 2] = n_acc;
-        stats_part[4 * slot + 3] = 0;
+        stats_part[4 * slot + 3] = n_tie;
         sum_part[slot] = s_dS;
     }
 }

@@ -200,9 +200,12 @@ enum { ACT_NONE = 0, ACT_SWEEP = 1, ACT_MERGE = 2, ACT_COMPACT = 3, ACT_DSWEEP =
 
 // device image of the public sweep statistics record
 struct sbp_sweep_stats_dev {
-    long long proposals, self_proposals, accepted, reserved;
+    long long proposals, self_proposals, accepted, near_ties;
     double sum_dS_accepted, dl_after;
 };
+// A decision is a near tie when its margin (-beta dS + ln H) - ln u lies within
+// this of zero: a differently ordered FP64 sum of the same terms could flip it.
+#define SBP_NEAR_TIE 1e-9
 #define SBP_MAX_DEGREE_DEV 16384
 
 // Index of the graph owning flat item i, given per-graph start offsets.

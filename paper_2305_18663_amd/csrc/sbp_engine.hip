@@ -119,7 +119,7 @@ __global__ void k_store_C(const GDev *__restrict__ G, int nG, int act, const int
 }
 __global__ void k_set_i32(int *p, int v) { *p = v; }
 __global__ void k_zero_stats(sbp_sweep_stats_dev *st) {
-    st->proposals = st->self_proposals = st->accepted = st->reserved = 0;
+    st->proposals = st->self_proposals = st->accepted = st->near_ties = 0;
     st->sum_dS_accepted = 0.0;
     st->dl_after = 0.0;
 }
@@ -136,46 +136,50 @@ __global__ void __launch_bounds__(256) k_sweep_stats_part(const signed char *__r
                                                          int n_batches, const int *__restrict__ skip,
                                                          long long *__restrict__ part,
                                                          double *__restrict__ sum_part) {
-    __shared__ long long a[4], b[4], c[4];
+    __shared__ long long a[4], b[4], c[4], e[4];
     __shared__ double d[4];
-    long long np = 0, ns = 0, na = 0;
+    long long np = 0, ns = 0, na = 0, nt = 0;
     double sd = 0.0;
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x;; i += (long long)gridDim.x * 256) {
         const long long v = batch + n_batches * i;
         if (v >= n) break;
         if (skip && skip[v] > 0) continue;  // a hub, moved before the batches
         ++np;
-        const int x = status[v];
+        const int x = status[v];  // -1 no-op, else accepted (bit 0) and near tie (bit 1)
         if (x < 0) ++ns;
-        if (x > 0) {
+        if (x >= 0 && (x & 1)) {
             ++na;
             sd += dS[v];
         }
+        if (x >= 0 && (x & 2)) ++nt;
     }
     np = wave_sum_i64(np);
     ns = wave_sum_i64(ns);
     na = wave_sum_i64(na);
+    nt = wave_sum_i64(nt);
     sd = wave_sum(sd);
     if ((threadIdx.x & 63) == 0) {
         a[threadIdx.x >> 6] = np;
         b[threadIdx.x >> 6] = ns;
         c[threadIdx.x >> 6] = na;
+        e[threadIdx.x >> 6] = nt;
         d[threadIdx.x >> 6] = sd;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        long long p = 0, q = 0, r = 0;
+        long long p = 0, q = 0, r = 0, u = 0;
         double t = 0.0;
         for (int w = 0; w < 4; ++w) {
             p += a[w];
             q += b[w];
             r += c[w];
+            u += e[w];
             t += d[w];
         }
         part[4 * blockIdx.x + 0] = p;
         part[4 * blockIdx.x + 1] = q;
         part[4 * blockIdx.x + 2] = r;
-        part[4 * blockIdx.x + 3] = 0;
+        part[4 * blockIdx.x + 3] = u;
         sum_part[blockIdx.x] = t;
     }
 }
@@ -184,22 +188,25 @@ __global__ void __launch_bounds__(64) k_sweep_stats_final(const long long *__res
                                                           const double *__restrict__ dl,
                                                           sbp_sweep_stats_dev *__restrict__ st) {
     const int lane = threadIdx.x;
-    long long p = 0, q = 0, r = 0;
+    long long p = 0, q = 0, r = 0, u = 0;
     double t = 0.0;
     for (int w = lane; w < nblk; w += 64) {
         p += part[4 * w + 0];
         q += part[4 * w + 1];
         r += part[4 * w + 2];
+        u += part[4 * w + 3];
         t += sum_part[w];
     }
     p = wave_sum_i64(p);
     q = wave_sum_i64(q);
     r = wave_sum_i64(r);
+    u = wave_sum_i64(u);
     t = wave_sum(t);
     if (lane == 0) {
         st->proposals += p;
         st->self_proposals += q;
         st->accepted += r;
+        st->near_ties += u;
         st->sum_dS_accepted += t;
         if (dl) st->dl_after = *dl;
     }

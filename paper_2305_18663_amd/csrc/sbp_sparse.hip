@@ -339,7 +339,8 @@ __device__ __forceinline__ void record_move(const GDev &d, int v, int r, const M
     if (tr.lnH) tr.lnH[u] = noop ? 0.0 : o.lnH;
     if (tr.margin) tr.margin[u] = noop ? 0.0 : o.margin;
     if (tr.accept) tr.accept[u] = acc ? 1 : 0;
-    if (tr.status) tr.status[u] = noop ? -1 : (acc ? 1 : 0);
+    // -1 no-op, else accepted (bit 0) and near tie (bit 1)
+    if (tr.status) tr.status[u] = noop ? -1 : (acc ? 1 : 0) + (fabs(o.margin) < SBP_NEAR_TIE ? 2 : 0);
 }
 
 constexpr int LEAF_WAVES = 4;

@@ -40,7 +40,7 @@ class SweepParams(ct.Structure):
 
 class SweepStats(ct.Structure):
     _fields_ = [("proposals", ct.c_int64), ("self_proposals", ct.c_int64), ("accepted", ct.c_int64),
-                ("reserved", ct.c_int64), ("sum_dS_accepted", ct.c_double), ("dl_after", ct.c_double)]
+                ("near_ties", ct.c_int64), ("sum_dS_accepted", ct.c_double), ("dl_after", ct.c_double)]
 
 
 class SweepTrace(ct.Structure):
@@ -294,7 +294,7 @@ def _stats_dict(st):
     raw = st.cpu().numpy()
     ints = raw[:4].view(np.int64)
     return dict(proposals=int(ints[0]), self_proposals=int(ints[1]), accepted=int(ints[2]),
-                sum_dS=float(raw[4]), dl_after=float(raw[5]))
+                near_ties=int(ints[3]), sum_dS=float(raw[4]), dl_after=float(raw[5]))
 
 
 class SweepGraph:

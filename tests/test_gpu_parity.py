@@ -665,6 +665,23 @@ def test_batches_in_step_change_nothing(kw):
         assert np.array_equal(a["trace"], b["trace"])
 
 
+@pytest.mark.parametrize("C,n_batches,n_hubs", [(7, 1, 0), (45, 1, 6), (45, 3, 0), (150, 1, 0), (150, 2, 4)])
+def test_sweep_stats_near_ties_and_totals(C, n_batches, n_hubs):
+    # the sweep totals agree with the sweep's own trace on both tiers: near
+    # ties are the proposals (not no-ops) with |margin| < 1e-9, accepted and
+    # no-op counts follow the per-vertex records
+    g = GRAPHS["dcsbm_2k"]()
+    dg = sbp.DeviceGraph(g)
+    lab = sbp.labels(gen.initial_labels(g.n, C, seed=C))
+    bm = sbp.sbp_build_blockmodel(dg, lab, C)
+    for k in range(6):
+        tr = sbp.sbp_nodal_sweep(dg, lab, C, bm, 33, k, n_batches=n_batches, n_hubs=n_hubs)
+        act = tr["margin"] != 0.0  # no-ops record a zero margin
+        assert tr["accepted"] == int(tr["accept"].sum())
+        assert tr["near_ties"] == int((act & (np.abs(tr["margin"]) < 1e-9)).sum())
+        assert tr["proposals"] == g.n
+
+
 def test_lookup_tables_change_nothing():
     # sparse-tier sweeps read M from a C x C table when C <= 2048; with the
     # tables switched off (binary searches of the rows) every result is equal
