@@ -1,12 +1,12 @@
 // sbp_dense.hip -- dense blockmodel tier for C <= 64 blocks (gfx950).
 //
-// With at most 64 blocks a wave64 lane owns one block t.  M (C x C int32,
-// Sec. II-A) and the per-block running sums of e_t. = M_t. + M_.t (the
-// proposal tables) live in global memory and are staged in LDS by every
-// workgroup of a sweep.  The blockmodel also keeps, for every edge end, the
-// block of its far end as one byte (C <= 64 fits), in CSR order, so that a
-// sweep reads its neighbour blocks as a contiguous stream instead of
-// gathering a label per end.  A single-batch sweep is three launches:
+// With at most 64 blocks M (C x C int32, Sec. II-A), f(M) and the block
+// degrees live in global memory and are staged in LDS by every workgroup of a
+// sweep; the proposal's running sums of e_t. = M_t. + M_.t come from the
+// staged M.  The blockmodel also keeps, for every edge end, the block of its
+// far end as one byte (C <= 64 fits), in CSR order, so that a sweep reads its
+// neighbour blocks as a contiguous stream instead of gathering a label per
+// end.  A single-batch sweep is three launches:
 //   eval   -- persistent grid over chunks of vertices: neighbour-block
 //             histograms in LDS from the end bytes, Philox proposal, DL change
 //             over the changed entries of M and the block degrees (Eq. 1-2),
@@ -20,9 +20,12 @@
 //             edge's entry once, which is why the per-vertex change vectors
 //             used for scoring cannot simply be added up); applies the labels.
 //             Workgroup deltas of M in LDS are flushed with integer atomics,
-//             so M does not depend on thread order;
-//   final  -- M += delta, block degrees, proposal tables, DL (one workgroup,
-//             fixed order).
+//             so M does not depend on thread order.  When few vertices moved
+//             it walks only their edges instead;
+//   final  -- M += delta, f(M), block degrees, DL (one workgroup, fixed
+//             order), sweep totals; its other workgroups write the moved
+//             vertices' new blocks into the end bytes that point at them
+//             after a move-driven update.
 // A sweep of several batches evaluates each batch against the labels (the
 // bytes would go stale within the sweep), walks only the moved vertices for
 // the delta, and recomputes the end bytes once at the end.
