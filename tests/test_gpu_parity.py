@@ -145,6 +145,17 @@ def test_sweep_parity(name, C):
     sweep_parity(g, lab0, C, seed=123, sweep=C)
 
 
+@pytest.mark.parametrize("C", [16, 17, 32, 33, 48, 49])
+@pytest.mark.parametrize("n_batches", [1, 3])
+def test_sweep_parity_at_capacity_edges(C, n_batches):
+    # the dense evaluation is built for block capacities 16, 32, 48 and 64
+    # (four-lane scoring groups up to 48, eight beyond): both sides of every
+    # boundary, one batch (end bytes) and several (labels gathered)
+    g = GRAPHS["dcsbm_2k"]()
+    lab0 = gen.initial_labels(g.n, C, seed=C + 5)
+    sweep_parity(g, lab0, C, seed=31, sweep=C, n_batches=n_batches)
+
+
 @pytest.mark.parametrize("C", [10, 80])
 @pytest.mark.parametrize("n_batches", [2, 7])
 def test_sweep_batches(C, n_batches):
