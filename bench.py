@@ -129,11 +129,87 @@ def make_graphs(specs, workers=16):
         return pool.map(_batch_member, specs, chunksize=4)
 
 
+def _oracle_batch_worker(core, go, nxt, lock, q, specs, deadline_s):
+    """One oracle process of the batch workload's CPU legs: waits for `go`,
+    then partitions graphs in the batch's order (the next index from the
+    shared counter) on its own core until `deadline_s` seconds have passed."""
+    from oracle import oracle as O
+    from paper_2305_18663_amd import gen
+    try:
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        pass
+    O.lib()
+    go.wait()
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < deadline_s:
+        with lock:
+            i = nxt.value
+            nxt.value += 1
+        if i >= len(specs):
+            break
+        n, gseed, pseed = specs[i]
+        g = gen.batch_graph(int(n), seed=int(gseed))
+        t0 = time.perf_counter()
+        r = O.partition(g, seed=int(pseed))
+        q.put((i, time.perf_counter() - t0, time.perf_counter() - t_start, int(r["C"]), float(r["dl"]), r["lab"]))
+    q.put(None)
+
+
+def _start_oracle_legs(specs, budget_s):
+    """The CPU legs of the batch workload, started before any GPU use: one
+    process on one core (sequential), then a pool with a process per host core
+    the benchmark may use (up to 16).  Each leg runs when its event is set."""
+    import multiprocessing as mp
+
+    from oracle import oracle as O
+    O.build()  # once, before the workers load it
+    ctx = mp.get_context("spawn")
+    _, _, allowed = host_cpu()
+    legs = {}
+    for name, cores in (("sequential", allowed[-1:]), ("pool", allowed[-min(16, len(allowed)):])):
+        go, q, nxt, lock = ctx.Event(), ctx.Queue(), ctx.Value("i", 0), ctx.Lock()
+        procs = [ctx.Process(target=_oracle_batch_worker, args=(c, go, nxt, lock, q, specs, budget_s), daemon=True)
+                 for c in cores]
+        for p in procs:
+            p.start()
+        legs[name] = (go, q, procs, nxt, lock)  # the parent keeps every shared object alive
+    return legs
+
+
+def _run_oracle_leg(leg, budget_s, grace_s=10.0):
+    """Sets the leg going and gathers (index, time, finish, C, DL, labels) per
+    graph finished within the budget and a short grace; a graph still running
+    then is dropped with its process."""
+    go, q, procs = leg[:3]
+    go.set()
+    out, ended = [], 0
+    t_end = time.perf_counter() + budget_s + grace_s
+    while ended < len(procs) and time.perf_counter() < t_end:
+        try:
+            item = q.get(timeout=max(0.1, t_end - time.perf_counter()))
+        except Exception:
+            break
+        if item is None:
+            ended += 1
+        else:
+            out.append(item)
+    for p in procs:
+        if p.is_alive():
+            p.terminate()
+        p.join()
+    return out
+
+
 def bench_batch(args):
-    """256 uneven DCSBM graphs: one batched partition vs 256 plain partitions."""
+    """256 uneven DCSBM graphs: one batched partition vs 256 plain partitions,
+    and the oracle's partitions of the same graphs on the host (a bounded leg
+    on one core and one on a process pool)."""
     import numpy as np
     from paper_2305_18663_amd import gen
     sizes = gen.batch_sizes(args.graphs, seed=3000)
+    specs = [(int(n), 3000 + i, 4000 + i) for i, n in enumerate(sizes)]
+    legs = _start_oracle_legs(specs, args.batch_oracle_budget) if args.batch_oracle_budget > 0 else None
     graphs = make_graphs([(n, 3000 + i) for i, n in enumerate(sizes)])
     progress(f"generated {len(graphs)} graphs")
     import torch
@@ -158,6 +234,29 @@ def bench_batch(args):
     t_p = time.perf_counter() - t0
     same = all(b["C"] == p["C"] and b["dl"] == p["dl"] and np.array_equal(b["lab"], p["lab"])
                for b, p in zip(batched, plain))
+    oracle = None
+    if legs:
+        model, nproc, allowed = host_cpu()
+        e_all = float(sum(g.e for g in graphs))
+        oracle = {"kind": "oracle", "budget_s": args.batch_oracle_budget, "cpu_model": model, "nproc": nproc}
+        for name in ("sequential", "pool"):
+            res = _run_oracle_leg(legs[name], args.batch_oracle_budget)
+            progress(f"oracle {name}: {len(res)} graphs")
+            if not res:
+                oracle[name] = {"graphs": 0}
+                continue
+            wall = max(r[2] for r in res)
+            busy = sum(r[1] for r in res)
+            e_done = float(sum(graphs[r[0]].e for r in res))
+            ident = all(r[3] == batched[r[0]]["C"] and np.array_equal(r[5], batched[r[0]]["lab"]) for r in res)
+            oracle[name] = {"cores": len(legs[name][2]), "graphs": len(res), "wall_s": wall,
+                            "graphs_per_s": len(res) / wall,
+                            "edge_share": e_done / e_all,
+                            # the whole batch at the sample's rate per edge end
+                            "est_all_graphs_s": wall * e_all / e_done,
+                            "identical_to_gpu": bool(ident),
+                            "sample": f"graphs in the batch's order until {args.batch_oracle_budget:.0f} s had passed; "
+                                      f"{busy:.1f} s of oracle time"}
     line = {"metric": "graphs/s, batched vs plain (256 uneven DCSBM graphs)", "value": len(dgs) / t_b,
             "unit": "graphs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
@@ -167,6 +266,8 @@ def bench_batch(args):
             "batched_s": t_b, "plain_s": t_p, "plain_graphs_per_s": len(dgs) / t_p, "speedup": t_p / t_b,
             "identical_results": bool(same),
             "mean_C": float(np.mean([b["C"] for b in batched]))}
+    if oracle:
+        line["cpu_baseline"] = oracle
     print(json.dumps(line), flush=True)
 
 
@@ -367,6 +468,8 @@ def main():
     ap.add_argument("--oracle-budget", type=float, default=120.0,
                     help="partition workloads: seconds the oracle leg may take before it is reported unfinished")
     ap.add_argument("--graphs", type=int, default=256)
+    ap.add_argument("--batch-oracle-budget", type=float, default=30.0,
+                    help="batch workload: seconds for each oracle leg (one core, then a process pool); 0 = none")
     ap.add_argument("--skip-partition", action="store_true", help="sparse1m: merges and sweeps only")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--calibration", type=int, default=100)
