@@ -969,7 +969,8 @@ __global__ void __launch_bounds__(256) k_to_dense(const ToDense *__restrict__ J,
 }
 
 // After the decisions of a single-batch sweep: every edge end once, chunks of
-// CH consecutive vertices per workgroup.  An out-edge (v, u) moves one count of
+// CHU consecutive vertices per workgroup (a workgroup per CU, each with a
+// balanced range of vertices, so mostly one chunk each).  An out-edge (v, u) moves one count of
 // M from (old v, old u) to (new v, new u) when either endpoint moved (LDS
 // delta, flushed with integer atomics); every end byte takes the far end's new
 // block; the labels of the chunk's vertices take their decisions.  The
@@ -977,9 +978,10 @@ __global__ void __launch_bounds__(256) k_to_dense(const ToDense *__restrict__ J,
 // workgroups need no ordering.  A thread takes 8 consecutive ends of the
 // chunk (its out-ends, then its in-ends) and issues all their loads and
 // decision gathers before any use.
-constexpr int CHU = 512;     // vertices per chunk of the update
+constexpr int CHU = 1024;    // vertices per chunk of the update
 constexpr int UPD_T = 1024;  // threads per update workgroup, one workgroup per CU
-static_assert(CHU < UPD_T, "a chunk's range ends are loaded by thread nv");
+constexpr int UPD_GRID_V = 512;  // at least this many vertices per workgroup (and at most one per CU)
+static_assert(CHU <= UPD_T, "a chunk's vertices are loaded by one thread each");
 // A thread takes an 8-aligned block of 8 consecutive end positions of the
 // chunk (its out-ends, then its in-ends): with VEC (16-byte aligned id
 // arrays) the ids come in two 16-byte loads, the end bytes in one 8-byte load
@@ -1081,7 +1083,6 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
         return;
     }
     for (int i = tid; i < CC; i += UPD_T) dl[i] = 0;
-    for (int i = tid; i < sl / 16; i += UPD_T) ((uint4 *)nbs)[i] = ((const uint4 *)nb)[i];
     const int nchunks = (g.n + CHU - 1) / CHU;
     for (int ci = 0;; ++ci) {
         int base, nv;
@@ -1096,17 +1097,25 @@ __global__ void __launch_bounds__(UPD_T) k_dense_update(GDev g, DenseBM bm, cons
             nv = min(CHU, g.n - base);
         }
         __syncthreads();
-        if (tid <= nv) {
-            const int v = base + tid;
-            op[tid] = g.out_ptr[v];
-            ip[tid] = g.in_ptr[v];
-            if (tid < nv) {
-                const int old = g.lab[v];
-                const unsigned x = nb[v];
-                a0[tid] = old;
-                a1[tid] = x != 0xffu ? (int)x : old;
-                if (x != 0xffu) g.lab[v] = (int)x;
+        // the chunk's head loads go out before the first chunk's copy of the
+        // staged decisions, so the two overlap
+        const bool hv = tid < nv;
+        const int vh = base + (hv ? tid : 0);
+        const int h_op = g.out_ptr[vh], h_ip = g.in_ptr[vh], h_old = g.lab[vh];
+        const unsigned h_x = nb[vh];
+        const int h_op1 = tid == nv - 1 ? g.out_ptr[vh + 1] : 0, h_ip1 = tid == nv - 1 ? g.in_ptr[vh + 1] : 0;
+        if (ci == 0)
+            for (int i = tid; i < sl / 16; i += UPD_T) ((uint4 *)nbs)[i] = ((const uint4 *)nb)[i];
+        if (hv) {
+            op[tid] = h_op;
+            ip[tid] = h_ip;
+            if (tid == nv - 1) {  // the ends of the chunk's ranges
+                op[nv] = h_op1;
+                ip[nv] = h_ip1;
             }
+            a0[tid] = h_old;
+            a1[tid] = h_x != 0xffu ? (int)h_x : h_old;
+            if (h_x != 0xffu) g.lab[vh] = (int)h_x;
         }
         __syncthreads();
         const int o0 = op[0], o1 = op[nv], i0 = ip[0], i1 = ip[nv];
@@ -1780,7 +1789,7 @@ int eval_grid(int C, int nbc, int nwg) {
 }
 int update_grid(int n, int nwg) {
     const int cus = nwg / 4 > 0 ? nwg / 4 : 1;
-    int ugrid = (n + CHU - 1) / CHU;
+    int ugrid = (n + UPD_GRID_V - 1) / UPD_GRID_V;
     if (ugrid > g_delta_wgs) ugrid = g_delta_wgs;
     if (ugrid > cus) ugrid = cus;
     return ugrid;
