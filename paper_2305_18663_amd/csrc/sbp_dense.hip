@@ -1749,8 +1749,15 @@ int dense_lds_per_block() {
         } else {
             v = 65536;
         }
-        (void)hipFuncSetAttribute((const void *)k_dense_update<true>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-        (void)hipFuncSetAttribute((const void *)k_dense_update<false>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        // the update's dynamic LDS may take all the CU has (it keeps no static
+        // LDS); where the runtime refuses that, the default limit holds
+        if (hipFuncSetAttribute((const void *)k_dense_update<true>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+                hipSuccess ||
+            hipFuncSetAttribute((const void *)k_dense_update<false>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            v = 65536;
+        }
         g_lds_block = v;
     }
     return g_lds_block;
