@@ -400,7 +400,7 @@ int sbp_engine_destroy(sbp_engine *eng);
  *   "dense_update_moved_share" a one-batch dense sweep updates M and the end
  *                            bytes from the moved vertices alone when at
  *                            most value/1024 of the vertices moved (default
- *                            128; 0..1024, or -1 for never), otherwise by a
+ *                            64; 0..1024, or -1 for never), otherwise by a
  *                            pass over every edge end
  *   "engine_dense_max_c"     engine sweep batches at C <= value (0..64) run on
  *                            the dense kernels (default 64; 0 = never)

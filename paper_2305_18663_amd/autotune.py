@@ -26,7 +26,7 @@ import sys
 
 import numpy as np
 
-DEFAULTS = {"dense_eval_workgroups": 0, "dense_delta_workgroups": 512, "dense_update_moved_share": 128}
+DEFAULTS = {"dense_eval_workgroups": 0, "dense_delta_workgroups": 512, "dense_update_moved_share": 64}
 CANDIDATES = {
     "dense_eval_workgroups": [0, 256, 512, 768],
     "dense_delta_workgroups": [256, 512, 1024],

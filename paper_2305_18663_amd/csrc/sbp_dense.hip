@@ -1778,7 +1778,7 @@ int dense_workgroups() {
 
 int g_eval_wgs = 0;     // workgroups of the evaluation grid (0 = one per chunk, capped by ws.nwg)
 int g_delta_wgs = 512;  // workgroups of the update grid
-int g_moved_share = 128;  // move-driven update when at most this many 1024ths of the vertices moved (< 0: never)
+int g_moved_share = 64;  // move-driven update when at most this many 1024ths of the vertices moved (< 0: never)
 constexpr int MIRROR_WGS = 256;  // workgroups writing mirror bytes after a move-driven update
 
 // Grid of the evaluation for C blocks and nbc batch vertices (every

@@ -237,7 +237,7 @@ def test_sweep_chain_update_modes(name, C, share):
         for k in range(5):
             cur = chain_step(g, dg, lab, cur, C, bm, 77, k)
     finally:
-        sbp.sbp_tune("dense_update_moved_share", 128)
+        sbp.sbp_tune("dense_update_moved_share", 64)
 
 
 def test_sweeps_200k_chain_default_update():
@@ -249,8 +249,10 @@ def test_sweeps_200k_chain_default_update():
     dg = sbp.DeviceGraph(g)
     lab = sbp.labels(gen.initial_labels(g.n, C, seed=seed))
     bm = sbp.sbp_build_blockmodel(dg, lab, C)
-    for k in range(60):
-        sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=False)
+    accepted = [sbp.sbp_nodal_sweep(dg, lab, C, bm, seed, k, trace=False, stats=True)["accepted"]
+                for k in range(60)]
+    # both update paths ran: the default threshold is 64/1024 of the vertices
+    assert max(accepted) * 1024 > 64 * g.n and min(accepted) * 1024 <= 64 * g.n, accepted
     cur = lab.cpu().numpy()
     for k in range(60, 62):
         cur = chain_step(g, dg, lab, cur, C, bm, seed, k)
@@ -275,7 +277,7 @@ def test_sweeps_200k_traced_equals_untraced(mode):
     lab0 = gen.initial_labels(g.n, C, seed=seed)
     la, lb = sbp.labels(lab0), sbp.labels(lab0)
     ba, bb = sbp.sbp_build_blockmodel(dg, la, C), sbp.sbp_build_blockmodel(dg, lb, C)
-    share = {"default": 128, "moved": 1024, "every_end": -1, "hubs": 128}[mode]
+    share = {"default": 64, "moved": 1024, "every_end": -1, "hubs": 64}[mode]
     sbp.sbp_tune("dense_update_moved_share", share)
     try:
         for k in range(24):
@@ -291,7 +293,7 @@ def test_sweeps_200k_traced_equals_untraced(mode):
         cur = lb.cpu().numpy()
         chain_step(g, dg, lb, cur, C, bb, seed, 24, n_hubs=n_hubs)
     finally:
-        sbp.sbp_tune("dense_update_moved_share", 128)
+        sbp.sbp_tune("dense_update_moved_share", 64)
 
 
 def hub_tail_graph(n=120_000):
@@ -375,7 +377,7 @@ def test_sweep_hybrid_chain():
             sbp.sbp_tune("dense_update_moved_share", 1024 if k % 2 else -1)
             cur = chain_step(g, dg, lab, cur, C, bm, 13, k, n_hubs=25)
     finally:
-        sbp.sbp_tune("dense_update_moved_share", 128)
+        sbp.sbp_tune("dense_update_moved_share", 64)
 
 
 @pytest.mark.parametrize("n_batches", [1, 2])
