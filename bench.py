@@ -30,8 +30,12 @@ EVAL_SOURCE = os.path.join(ROOT, "paper_2305_18663_amd", "csrc", "sbp_dense.hip"
 
 
 def source_hash():
+    """Hash of the evaluation kernel's source and its compile flags."""
     import hashlib
-    return hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()[:16]
+    from paper_2305_18663_amd import build
+    h = hashlib.sha256(open(EVAL_SOURCE, "rb").read())
+    h.update(" ".join(build.flags_of(os.path.basename(EVAL_SOURCE))).encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
